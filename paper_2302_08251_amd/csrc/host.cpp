@@ -1,0 +1,594 @@
+// Host runtime: descriptor validation, blob sizing, views, copy planning
+// and dispatch of the tile kernels.
+#include "host.hpp"
+
+#include <cstdarg>
+#include <cstring>
+
+#include "kernels.hpp"
+
+namespace lm {
+
+static thread_local std::string g_error;
+
+llama_status fail(llama_status s, const std::string& msg) {
+  g_error = msg;
+  return s;
+}
+
+void clear_error() { g_error.clear(); }
+
+bool scalar_valid(int t) { return t >= LLAMA_F32 && t <= LLAMA_BF16; }
+
+uint32_t scalar_size(llama_scalar t) {
+  switch (t) {
+    case LLAMA_I8: case LLAMA_U8: return 1;
+    case LLAMA_I16: case LLAMA_U16: case LLAMA_F16: case LLAMA_BF16: return 2;
+    case LLAMA_F32: case LLAMA_I32: case LLAMA_U32: return 4;
+    case LLAMA_F64: case LLAMA_I64: case LLAMA_U64: return 8;
+  }
+  return 0;
+}
+
+bool scalar_is_float(llama_scalar t) {
+  return t == LLAMA_F32 || t == LLAMA_F64 || t == LLAMA_F16 || t == LLAMA_BF16;
+}
+
+bool scalar_is_signed(llama_scalar t) {
+  return t == LLAMA_I8 || t == LLAMA_I16 || t == LLAMA_I32 || t == LLAMA_I64;
+}
+
+static void float_bits(llama_scalar t, uint32_t& E, uint32_t& M) {
+  switch (t) {
+    case LLAMA_F16: E = 5; M = 10; return;
+    case LLAMA_BF16: E = 8; M = 7; return;
+    case LLAMA_F32: E = 8; M = 23; return;
+    case LLAMA_F64: E = 11; M = 52; return;
+    default: E = M = 0;
+  }
+}
+
+static bool is_physical(llama_map_kind k) {
+  return k == LLAMA_MAP_AOS || k == LLAMA_MAP_SOA_SB || k == LLAMA_MAP_SOA_MB || k == LLAMA_MAP_AOSOA;
+}
+
+static uint64_t packed_size(const Rec& r) {
+  uint64_t s = 0;
+  for (auto t : r) s += scalar_size(t);
+  return s;
+}
+
+static uint64_t aligned_size(const Rec& r) {
+  uint64_t o = 0, maxs = 1;
+  for (auto t : r) {
+    uint64_t s = scalar_size(t);
+    o = (o + s - 1) / s * s + s;
+    if (s > maxs) maxs = s;
+  }
+  return (o + maxs - 1) / maxs * maxs;
+}
+
+static Rec byte_record(const Rec& r) { return Rec(packed_size(r), LLAMA_U8); }
+
+static const char* kind_name(int k) {
+  static const char* names[] = {"AOS", "SOA_SB", "SOA_MB", "AOSOA", "BYTESPLIT", "CHANGETYPE",
+                                "BITPACK_INT_SOA", "BITPACK_FLOAT_SOA"};
+  return (k >= 0 && k < 8) ? names[k] : "?";
+}
+
+llama_status copy_mapping(const Rec& rec, const llama_mapping* map, MapDesc& out, int depth) {
+  if (!map) return fail(LLAMA_ERR_INVALID_ARG, "mapping descriptor is NULL");
+  if ((int)map->kind < 0 || (int)map->kind > 7)
+    return fail(LLAMA_ERR_INVALID_ARG, "unknown mapping kind " + std::to_string((int)map->kind));
+  out.kind = map->kind;
+  out.lanes = map->lanes;
+  out.bits = map->bits;
+  out.exp_bits = map->exp_bits;
+  out.man_bits = map->man_bits;
+  out.flags = map->flags;
+  if (map->flags & ~LLAMA_FLAG_AOS_PACKED) return fail(LLAMA_ERR_INVALID_ARG, "unknown mapping flags");
+  switch (map->kind) {
+    case LLAMA_MAP_AOS:
+    case LLAMA_MAP_SOA_SB:
+    case LLAMA_MAP_SOA_MB:
+      return LLAMA_OK;
+    case LLAMA_MAP_AOSOA:
+      if (map->lanes == 0) return fail(LLAMA_ERR_INVALID_ARG, "AOSOA needs lanes >= 1");
+      return LLAMA_OK;
+    case LLAMA_MAP_BYTESPLIT: {
+      if (!map->inner) return fail(LLAMA_ERR_INVALID_ARG, "BYTESPLIT needs an inner mapping");
+      if (!is_physical(map->inner->kind))
+        return fail(LLAMA_ERR_INVALID_ARG, std::string("BYTESPLIT inner mapping must be AOS, SOA_SB, SOA_MB or AOSOA, got ") +
+                                               kind_name(map->inner->kind));
+      out.inner.reset(new MapDesc);
+      return copy_mapping(byte_record(rec), map->inner, *out.inner, depth + 1);
+    }
+    case LLAMA_MAP_CHANGETYPE: {
+      if (!map->stored_types) return fail(LLAMA_ERR_INVALID_ARG, "CHANGETYPE needs stored_types");
+      if (!map->inner) return fail(LLAMA_ERR_INVALID_ARG, "CHANGETYPE needs an inner mapping");
+      if (!is_physical(map->inner->kind) && map->inner->kind != LLAMA_MAP_BYTESPLIT)
+        return fail(LLAMA_ERR_INVALID_ARG, "CHANGETYPE inner mapping must be physical or BYTESPLIT");
+      out.stored.assign(map->stored_types, map->stored_types + rec.size());
+      for (size_t f = 0; f < rec.size(); ++f) {
+        if (!scalar_valid(out.stored[f])) return fail(LLAMA_ERR_INVALID_ARG, "invalid stored type");
+        llama_scalar a = rec[f], b = out.stored[f];
+        if (a == b) continue;
+        if (scalar_is_float(a) != scalar_is_float(b))
+          return fail(LLAMA_ERR_INVALID_ARG, "CHANGETYPE converts float to float or integer to integer only");
+        if (scalar_is_float(a)) {
+          uint32_t Ea, Ma, Eb, Mb;
+          float_bits(a, Ea, Ma);
+          float_bits(b, Eb, Mb);
+          if (!((Eb >= Ea && Mb >= Ma) || (Eb <= Ea && Mb <= Ma)))
+            return fail(LLAMA_ERR_INVALID_ARG, "CHANGETYPE between these float formats is neither widening nor narrowing");
+        }
+      }
+      out.inner.reset(new MapDesc);
+      return copy_mapping(out.stored, map->inner, *out.inner, depth + 1);
+    }
+    case LLAMA_MAP_BITPACK_INT_SOA:
+      for (auto t : rec) {
+        if (scalar_is_float(t)) return fail(LLAMA_ERR_INVALID_ARG, "BITPACK_INT_SOA needs integer fields");
+        if (map->bits < 1 || map->bits > 8 * scalar_size(t))
+          return fail(LLAMA_ERR_INVALID_ARG, "BITPACK_INT_SOA bits must be in [1, bit width of every field]");
+      }
+      return LLAMA_OK;
+    case LLAMA_MAP_BITPACK_FLOAT_SOA:
+      for (auto t : rec) {
+        if (!scalar_is_float(t)) return fail(LLAMA_ERR_INVALID_ARG, "BITPACK_FLOAT_SOA needs float fields");
+        uint32_t E, M;
+        float_bits(t, E, M);
+        if (map->exp_bits < 2 || map->exp_bits > E || map->man_bits > M)
+          return fail(LLAMA_ERR_INVALID_ARG,
+                      "BITPACK_FLOAT_SOA needs 2 <= exp_bits <= E and man_bits <= M of every field type");
+      }
+      return LLAMA_OK;
+  }
+  return fail(LLAMA_ERR_INVALID_ARG, "unknown mapping kind");
+}
+
+static uint32_t code_bits(const MapDesc& m) {
+  return m.kind == LLAMA_MAP_BITPACK_INT_SOA ? m.bits : 1 + m.exp_bits + m.man_bits;
+}
+
+uint32_t blob_count(const Rec& rec, const MapDesc& m) {
+  switch (m.kind) {
+    case LLAMA_MAP_AOS: case LLAMA_MAP_SOA_SB: case LLAMA_MAP_AOSOA: return 1;
+    case LLAMA_MAP_SOA_MB: case LLAMA_MAP_BITPACK_INT_SOA: case LLAMA_MAP_BITPACK_FLOAT_SOA:
+      return (uint32_t)rec.size();
+    case LLAMA_MAP_BYTESPLIT: return blob_count(byte_record(rec), *m.inner);
+    case LLAMA_MAP_CHANGETYPE: return blob_count(m.stored, *m.inner);
+  }
+  return 0;
+}
+
+uint64_t blob_size(const Rec& rec, const MapDesc& m, uint64_t n, uint32_t b) {
+  switch (m.kind) {
+    case LLAMA_MAP_AOS: return n * ((m.flags & LLAMA_FLAG_AOS_PACKED) ? packed_size(rec) : aligned_size(rec));
+    case LLAMA_MAP_SOA_SB: return n * packed_size(rec);
+    case LLAMA_MAP_SOA_MB: return n * scalar_size(rec[b]);
+    case LLAMA_MAP_AOSOA: return (n + m.lanes - 1) / m.lanes * m.lanes * packed_size(rec);
+    case LLAMA_MAP_BYTESPLIT: return blob_size(byte_record(rec), *m.inner, n, b);
+    case LLAMA_MAP_CHANGETYPE: return blob_size(m.stored, *m.inner, n, b);
+    case LLAMA_MAP_BITPACK_INT_SOA:
+    case LLAMA_MAP_BITPACK_FLOAT_SOA: return 4 * ((n * code_bits(m) + 31) / 32);
+  }
+  return 0;
+}
+
+uint64_t mapped_bytes(const Rec& rec, const MapDesc& m, uint64_t n) {
+  switch (m.kind) {
+    case LLAMA_MAP_AOS: case LLAMA_MAP_SOA_SB: case LLAMA_MAP_SOA_MB: case LLAMA_MAP_AOSOA:
+      return n * packed_size(rec);
+    case LLAMA_MAP_BYTESPLIT: return n * packed_size(rec);
+    case LLAMA_MAP_CHANGETYPE: return n * packed_size(m.stored);
+    case LLAMA_MAP_BITPACK_INT_SOA:
+    case LLAMA_MAP_BITPACK_FLOAT_SOA: return rec.size() * ((n * code_bits(m) + 7) / 8);
+  }
+  return 0;
+}
+
+static llama_status read_record(const llama_record* r, Rec& out) {
+  if (!r) return fail(LLAMA_ERR_INVALID_ARG, "record is NULL");
+  if (r->n_fields < 1 || r->n_fields > kMaxFields)
+    return fail(LLAMA_ERR_INVALID_ARG, "record needs 1..64 leaf fields");
+  if (!r->types) return fail(LLAMA_ERR_INVALID_ARG, "record types are NULL");
+  out.assign(r->types, r->types + r->n_fields);
+  for (auto t : out)
+    if (!scalar_valid(t)) return fail(LLAMA_ERR_INVALID_ARG, "invalid leaf type " + std::to_string((int)t));
+  return LLAMA_OK;
+}
+
+static llama_status read_extents(uint32_t rank, const uint64_t* ext, uint64_t& n) {
+  if (rank < 1 || rank > 8) return fail(LLAMA_ERR_INVALID_ARG, "rank must be 1..8");
+  if (!ext) return fail(LLAMA_ERR_INVALID_ARG, "extents are NULL");
+  n = 1;
+  for (uint32_t d = 0; d < rank; ++d) {
+    if (ext[d] != 0 && n > UINT64_MAX / ext[d])
+      return fail(LLAMA_ERR_INDEX_OVERFLOW, "extents overflow 64 bits");
+    n *= ext[d];
+  }
+  // keep byte sizes representable: n * (up to 512 bytes per record)
+  if (n > (UINT64_MAX >> 10)) return fail(LLAMA_ERR_INDEX_OVERFLOW, "too many records");
+  return LLAMA_OK;
+}
+
+static uint64_t index_max(llama_index_type t) {
+  switch (t) {
+    case LLAMA_IDX_I16: return 0x7FFFull;
+    case LLAMA_IDX_U16: return 0xFFFFull;
+    case LLAMA_IDX_I32: return 0x7FFFFFFFull;
+    case LLAMA_IDX_U32: return 0xFFFFFFFFull;
+    case LLAMA_IDX_I64: return 0x7FFFFFFFFFFFFFFFull;
+    case LLAMA_IDX_U64: return UINT64_MAX;
+  }
+  return 0;
+}
+
+Div make_div(uint32_t d) {
+  Div r{};
+  r.d = d ? d : 1;
+  if ((r.d & (r.d - 1)) == 0) {
+    r.pow2 = 1;
+    r.sh = (uint32_t)__builtin_ctz(r.d);
+    r.m = 0;
+  } else {
+    r.pow2 = 0;
+    r.sh = 0;
+    r.m = (uint32_t)(((1ull << 32) + r.d - 1) / r.d);
+  }
+  return r;
+}
+
+static uint32_t log2u(uint32_t x) { return (uint32_t)__builtin_ctz(x); }
+
+// Structural description of a physical mapping (possibly a Bytesplit)
+// over a storage record of uniform element size `es`.
+static llama_status physical_side(const MapDesc& m, uint32_t nf, uint32_t es, Side& s) {
+  const MapDesc* p = &m;
+  uint32_t cs = es, ncols = nf;
+  if (m.kind == LLAMA_MAP_BYTESPLIT) {
+    p = m.inner.get();
+    cs = 1;
+    ncols = nf * es;
+  }
+  s.cs = cs;
+  s.log2cs = log2u(cs);
+  s.ncols = ncols;
+  s.rec_bytes = ncols * cs;
+  s.mb = 0;
+  s.lanes = 1;
+  switch (p->kind) {
+    case LLAMA_MAP_AOS: s.layout = LY_AOS; break;
+    case LLAMA_MAP_SOA_SB: s.layout = LY_PLANAR; break;
+    case LLAMA_MAP_SOA_MB:
+      s.layout = LY_PLANAR;
+      s.mb = 1;
+      if (ncols > kMaxCols) return fail(LLAMA_ERR_UNSUPPORTED, "more than 64 blobs in one view");
+      break;
+    case LLAMA_MAP_AOSOA:
+      s.layout = LY_AOSOA;
+      s.lanes = p->lanes;
+      break;
+    default: return fail(LLAMA_ERR_UNSUPPORTED, "unsupported inner mapping");
+  }
+  return LLAMA_OK;
+}
+
+static llama_status uniform_type(const Rec& r, llama_scalar& t, bool same_type, const char* what) {
+  t = r[0];
+  for (auto x : r) {
+    if (scalar_size(x) != scalar_size(t))
+      return fail(LLAMA_ERR_UNSUPPORTED, std::string("the GPU tile engine needs leaves of equal size (") + what + ")");
+    if (same_type && x != t)
+      return fail(LLAMA_ERR_UNSUPPORTED, std::string("the GPU path needs leaves of one type (") + what + ")");
+  }
+  return LLAMA_OK;
+}
+
+llama_status make_side(const llama_view* v, Side& s, llama_scalar& user_t, llama_scalar& stored_t) {
+  std::memset(&s, 0, sizeof(s));
+  const MapDesc& m = v->map;
+  const uint32_t nf = (uint32_t)v->rec.size();
+  llama_status st;
+  const bool need_same = m.kind == LLAMA_MAP_CHANGETYPE || m.kind == LLAMA_MAP_BITPACK_INT_SOA ||
+                         m.kind == LLAMA_MAP_BITPACK_FLOAT_SOA;
+  if ((st = uniform_type(v->rec, user_t, need_same, "record")) != LLAMA_OK) return st;
+  stored_t = user_t;
+  s.vkind = VK_RAW;
+  s.n = v->n;
+  s.n_mod16 = (uint32_t)(v->n & 15u);
+  switch (m.kind) {
+    case LLAMA_MAP_AOS: case LLAMA_MAP_SOA_SB: case LLAMA_MAP_SOA_MB: case LLAMA_MAP_AOSOA:
+    case LLAMA_MAP_BYTESPLIT:
+      if ((st = physical_side(m, nf, scalar_size(user_t), s)) != LLAMA_OK) return st;
+      s.es = scalar_size(user_t);
+      break;
+    case LLAMA_MAP_CHANGETYPE:
+      if ((st = uniform_type(m.stored, stored_t, true, "stored types")) != LLAMA_OK) return st;
+      if ((st = physical_side(*m.inner, nf, scalar_size(stored_t), s)) != LLAMA_OK) return st;
+      s.es = scalar_size(stored_t);
+      s.vkind = stored_t == user_t ? VK_RAW : VK_CONV;
+      break;
+    case LLAMA_MAP_BITPACK_INT_SOA:
+    case LLAMA_MAP_BITPACK_FLOAT_SOA:
+      s.layout = LY_STREAM;
+      s.vkind = m.kind == LLAMA_MAP_BITPACK_INT_SOA ? VK_INT : VK_FLOAT;
+      s.bits = code_bits(m);
+      s.exp_bits = m.exp_bits;
+      s.man_bits = m.man_bits;
+      s.is_signed = scalar_is_signed(user_t);
+      s.ncols = nf;
+      s.cs = 4;
+      s.log2cs = 2;
+      s.es = scalar_size(user_t);
+      if (s.bits > 32) return fail(LLAMA_ERR_UNSUPPORTED, "the GPU path packs codes of at most 32 bits");
+      if (nf > kMaxCols) return fail(LLAMA_ERR_UNSUPPORTED, "more than 64 blobs in one view");
+      break;
+  }
+  s.blob_size = v->blob_bytes.empty() ? 0 : v->blob_bytes[0];
+  for (size_t b = 0; b < v->blobs.size() && b < kMaxCols; ++b) s.blob[b] = v->blobs[b];
+  s.div_S = make_div(s.rec_bytes);
+  s.div_L = make_div(s.lanes);
+  s.div_LS = make_div(s.lanes * s.rec_bytes);
+  s.div_Lcs = make_div(s.lanes * s.cs);
+  s.div_B = make_div(s.bits ? s.bits : 1);
+  return LLAMA_OK;
+}
+
+static uint64_t gcd64(uint64_t a, uint64_t b) {
+  while (b) {
+    uint64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+static uint64_t lcm64(uint64_t a, uint64_t b) { return a / gcd64(a, b) * b; }
+
+uint64_t tile_granule(const Side& s, const Side& d) {
+  uint64_t g = 128;
+  if (s.layout == LY_AOSOA) g = lcm64(g, s.lanes);
+  if (d.layout == LY_AOSOA) g = lcm64(g, d.lanes);
+  return g;
+}
+
+uint32_t tile_lds_bytes(const Side& s, uint32_t tile) {
+  switch (s.layout) {
+    case LY_AOS: case LY_AOSOA: return tile * s.rec_bytes;
+    case LY_PLANAR: return s.ncols * (tile * s.cs + 16u);
+    default: return s.ncols * (tile * s.bits / 8u + 16u);
+  }
+}
+
+static uint32_t lds_stride(const Side& s, uint32_t tile) {
+  if (s.layout == LY_PLANAR) return tile * s.cs + 16u;
+  if (s.layout == LY_STREAM) return tile * s.bits / 8u + 16u;
+  return 0;
+}
+
+static Codec codec_of(llama_scalar t) {
+  switch (t) {
+    case LLAMA_U8: return CD_U8;
+    case LLAMA_I8: return CD_I8;
+    case LLAMA_U16: return CD_U16;
+    case LLAMA_I16: return CD_I16;
+    case LLAMA_U32: return CD_U32;
+    case LLAMA_I32: return CD_I32;
+    case LLAMA_U64: return CD_U64;
+    case LLAMA_I64: return CD_I64;
+    case LLAMA_F32: return CD_F32;
+    default: return CD_F64;
+  }
+}
+
+llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama_launch_params* p,
+                       Plan& plan) {
+  if (!src || !dst) return fail(LLAMA_ERR_INVALID_ARG, "view is NULL");
+  if (src->rec != dst->rec) return fail(LLAMA_ERR_RECORD_MISMATCH, "source and destination records differ");
+  if (src->n != dst->n) return fail(LLAMA_ERR_RECORD_MISMATCH, "source and destination record counts differ");
+  plan = Plan{};
+  llama_status st;
+  llama_scalar su, ss, du, ds;
+  Side& S = plan.args.src;
+  Side& D = plan.args.dst;
+  if ((st = make_side(src, S, su, ss)) != LLAMA_OK) return st;
+  if ((st = make_side(dst, D, du, ds)) != LLAMA_OK) return st;
+  const bool sstream = S.layout == LY_STREAM, dstream = D.layout == LY_STREAM;
+  if (sstream && dstream) return fail(LLAMA_ERR_UNSUPPORTED, "copy between two bit-packed views");
+  if (dstream) {
+    if (S.vkind != VK_RAW) return fail(LLAMA_ERR_UNSUPPORTED, "pack needs a physical source");
+    plan.kind = PK_PACK;
+    plan.unit = 4;
+    plan.args.codec = codec_of(su);
+  } else if (sstream) {
+    if (D.vkind != VK_RAW) return fail(LLAMA_ERR_UNSUPPORTED, "unpack needs a physical destination");
+    plan.kind = PK_UNPACK;
+    plan.unit = D.cs;
+    plan.args.codec = codec_of(su);
+  } else if (S.vkind == VK_RAW && D.vkind == VK_RAW) {
+    plan.kind = PK_RAW;
+    plan.unit = S.cs < D.cs ? S.cs : D.cs;
+  } else if (S.vkind == VK_CONV && D.vkind == VK_CONV) {
+    return fail(LLAMA_ERR_UNSUPPORTED, "copy between two ChangeType views with conversions");
+  } else {
+    const llama_scalar from = S.vkind == VK_CONV ? ss : su;
+    const llama_scalar to = D.vkind == VK_CONV ? ds : du;
+    plan.kind = PK_CONV;
+    plan.unit = D.cs;
+    if (from == LLAMA_F64 && to == LLAMA_F32) plan.args.conv = CV_F64_F32;
+    else if (from == LLAMA_F32 && to == LLAMA_F64) plan.args.conv = CV_F32_F64;
+    else return fail(LLAMA_ERR_UNSUPPORTED, "the GPU path converts between F64 and F32 only");
+  }
+  const uint64_t gran = tile_granule(S, D);
+  uint64_t tile = p && p->tile_records ? p->tile_records : 0;
+  if (tile) {
+    if (tile % gran) return fail(LLAMA_ERR_INVALID_ARG, "tile_records must be a multiple of " + std::to_string(gran));
+  } else {
+    // about 16 KiB of LDS per tile
+    const uint64_t per = tile_lds_bytes(S, (uint32_t)gran);
+    uint64_t k = per ? (16384 / per) : 1;
+    if (k < 1) k = 1;
+    tile = gran * k;
+  }
+  if (tile > 65536) return fail(LLAMA_ERR_INVALID_ARG, "tile_records must be <= 65536");
+  const uint64_t lds = tile_lds_bytes(S, (uint32_t)tile);
+  if (lds > kMaxTileLds)
+    return fail(tile == gran ? LLAMA_ERR_UNSUPPORTED : LLAMA_ERR_INVALID_ARG,
+                "a tile of " + std::to_string(tile) + " records needs " + std::to_string(lds) +
+                    " bytes of LDS (limit 65536); reduce the tile or the AoSoA lane count");
+  if (tile * D.rec_bytes > kMaxTileLds * 2ull && D.layout != LY_STREAM)
+    return fail(LLAMA_ERR_INVALID_ARG, "destination tile too large");
+  S.lds_stride = lds_stride(S, (uint32_t)tile);
+  D.lds_stride = lds_stride(D, (uint32_t)tile);
+  plan.args.tile = (uint32_t)tile;
+  plan.ntiles = (src->n + tile - 1) / tile;
+  if (plan.ntiles > 0xFFFFFFFFull) return fail(LLAMA_ERR_INDEX_OVERFLOW, "too many tiles");
+  plan.args.ntiles_lo = (uint32_t)plan.ntiles;
+  plan.grid = (p && p->grid) ? (uint32_t)(p->grid < plan.ntiles ? p->grid : plan.ntiles) : (uint32_t)plan.ntiles;
+  plan.lds = (uint32_t)lds;
+  plan.alg_bytes = mapped_bytes(src->rec, src->map, src->n) + mapped_bytes(dst->rec, dst->map, dst->n);
+  return LLAMA_OK;
+}
+
+llama_status launch_plan(const Plan& plan, hipStream_t st) {
+  if (plan.ntiles == 0) return LLAMA_OK;
+  hipError_t e = hipSuccess;
+  switch (plan.kind) {
+    case PK_RAW: e = launch_raw(plan.args, plan.unit, plan.grid, plan.lds, st); break;
+    case PK_CONV: e = launch_conv(plan.args, plan.unit, plan.grid, plan.lds, st); break;
+    case PK_PACK: e = launch_pack(plan.args, plan.grid, plan.lds, st); break;
+    case PK_UNPACK: e = launch_unpack(plan.args, plan.unit, plan.grid, plan.lds, st); break;
+  }
+  if (e != hipSuccess) return fail(LLAMA_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return LLAMA_OK;
+}
+
+}  // namespace lm
+
+using namespace lm;
+
+extern "C" {
+
+const char* llama_last_error(void) { return g_error.c_str(); }
+
+const char* llama_version(void) { return "llama-mi 0.1 (gfx950)"; }
+
+llama_status llama_mapping_blob_count(const llama_record* rec, const llama_mapping* map, uint32_t* n) {
+  clear_error();
+  Rec r;
+  MapDesc m;
+  llama_status st;
+  if ((st = read_record(rec, r)) != LLAMA_OK) return st;
+  if ((st = copy_mapping(r, map, m)) != LLAMA_OK) return st;
+  if (!n) return fail(LLAMA_ERR_INVALID_ARG, "output pointer is NULL");
+  *n = blob_count(r, m);
+  return LLAMA_OK;
+}
+
+llama_status llama_mapping_blob_size(const llama_record* rec, const llama_mapping* map, uint32_t rank,
+                                     const uint64_t* extents, uint32_t blob, uint64_t* bytes) {
+  clear_error();
+  Rec r;
+  MapDesc m;
+  uint64_t n;
+  llama_status st;
+  if ((st = read_record(rec, r)) != LLAMA_OK) return st;
+  if ((st = copy_mapping(r, map, m)) != LLAMA_OK) return st;
+  if ((st = read_extents(rank, extents, n)) != LLAMA_OK) return st;
+  if (!bytes) return fail(LLAMA_ERR_INVALID_ARG, "output pointer is NULL");
+  if (blob >= blob_count(r, m)) return fail(LLAMA_ERR_INVALID_ARG, "blob index out of range");
+  *bytes = blob_size(r, m, n, blob);
+  return LLAMA_OK;
+}
+
+llama_status llama_view_create(const llama_record* rec, const llama_mapping* map, uint32_t rank,
+                               const uint64_t* extents, llama_index_type index_type, void* const* blobs,
+                               const uint64_t* blob_bytes, uint32_t n_blobs, llama_view** out) {
+  clear_error();
+  if (!out) return fail(LLAMA_ERR_INVALID_ARG, "output pointer is NULL");
+  *out = nullptr;
+  std::unique_ptr<llama_view> v(new llama_view);
+  llama_status st;
+  if ((st = read_record(rec, v->rec)) != LLAMA_OK) return st;
+  if ((st = copy_mapping(v->rec, map, v->map)) != LLAMA_OK) return st;
+  if ((st = read_extents(rank, extents, v->n)) != LLAMA_OK) return st;
+  v->rank = rank;
+  for (uint32_t d = 0; d < rank; ++d) v->extents[d] = extents[d];
+  if ((int)index_type < LLAMA_IDX_I16 || (int)index_type > LLAMA_IDX_U64)
+    return fail(LLAMA_ERR_INVALID_ARG, "invalid index type");
+  v->index_type = index_type;
+  const uint64_t imax = index_max(index_type);
+  if (v->n > 0 && v->n - 1 > imax)
+    return fail(LLAMA_ERR_INDEX_OVERFLOW, "record count does not fit the index type");
+  const uint32_t nb = blob_count(v->rec, v->map);
+  if (n_blobs != nb)
+    return fail(LLAMA_ERR_INVALID_ARG, "mapping uses " + std::to_string(nb) + " blobs, got " + std::to_string(n_blobs));
+  if (!blobs || !blob_bytes) return fail(LLAMA_ERR_INVALID_ARG, "blobs or blob_bytes is NULL");
+  for (uint32_t b = 0; b < nb; ++b) {
+    const uint64_t need = blob_size(v->rec, v->map, v->n, b);
+    if (need > 0 && need - 1 > imax)
+      return fail(LLAMA_ERR_INDEX_OVERFLOW, "blob " + std::to_string(b) + " of " + std::to_string(need) +
+                                                " bytes does not fit the index type");
+    if (need > 0 && !blobs[b]) return fail(LLAMA_ERR_INVALID_ARG, "blob " + std::to_string(b) + " is NULL");
+    if (((uintptr_t)blobs[b]) & 15u)
+      return fail(LLAMA_ERR_ALIGNMENT, "blob " + std::to_string(b) + " is not 16-byte aligned");
+    if (blob_bytes[b] < need)
+      return fail(LLAMA_ERR_NO_MEMORY, "blob " + std::to_string(b) + " has " + std::to_string(blob_bytes[b]) +
+                                           " bytes, the mapping needs " + std::to_string(need));
+    v->blobs.push_back(blobs[b]);
+    v->blob_bytes.push_back(need);
+  }
+  *out = v.release();
+  return LLAMA_OK;
+}
+
+llama_status llama_view_destroy(llama_view* view) {
+  clear_error();
+  delete view;
+  return LLAMA_OK;
+}
+
+llama_status llama_view_records(const llama_view* view, uint64_t* n) {
+  clear_error();
+  if (!view || !n) return fail(LLAMA_ERR_INVALID_ARG, "NULL argument");
+  *n = view->n;
+  return LLAMA_OK;
+}
+
+llama_status llama_copy_ex(const llama_view* src, llama_view* dst, const llama_launch_params* params,
+                           void* stream) {
+  clear_error();
+  Plan plan;
+  llama_status st = plan_copy(src, dst, params, plan);
+  if (st != LLAMA_OK) return st;
+  return launch_plan(plan, (hipStream_t)stream);
+}
+
+llama_status llama_copy(const llama_view* src, llama_view* dst, void* stream) {
+  return llama_copy_ex(src, dst, nullptr, stream);
+}
+
+static bool computed(const llama_view* v) {
+  return v->map.kind == LLAMA_MAP_CHANGETYPE || v->map.kind == LLAMA_MAP_BITPACK_INT_SOA ||
+         v->map.kind == LLAMA_MAP_BITPACK_FLOAT_SOA;
+}
+
+llama_status llama_pack(const llama_view* src, llama_view* dst, void* stream) {
+  clear_error();
+  if (!src || !dst) return fail(LLAMA_ERR_INVALID_ARG, "view is NULL");
+  if (computed(src) || !computed(dst))
+    return fail(LLAMA_ERR_UNSUPPORTED, "pack needs a physical source and a computed destination");
+  return llama_copy_ex(src, dst, nullptr, stream);
+}
+
+llama_status llama_unpack(const llama_view* src, llama_view* dst, void* stream) {
+  clear_error();
+  if (!src || !dst) return fail(LLAMA_ERR_INVALID_ARG, "view is NULL");
+  if (!computed(src) || computed(dst))
+    return fail(LLAMA_ERR_UNSUPPORTED, "unpack needs a computed source and a physical destination");
+  return llama_copy_ex(src, dst, nullptr, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+// Host-side view representation, validation and copy planning.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace lm {
+
+// Deep copy of a mapping descriptor.
+struct MapDesc {
+  llama_map_kind kind = LLAMA_MAP_AOS;
+  uint32_t lanes = 0, bits = 0, exp_bits = 0, man_bits = 0, flags = 0;
+  std::vector<llama_scalar> stored;
+  std::unique_ptr<MapDesc> inner;
+};
+
+using Rec = std::vector<llama_scalar>;
+
+uint32_t scalar_size(llama_scalar t);
+bool scalar_valid(int t);
+bool scalar_is_float(llama_scalar t);
+bool scalar_is_signed(llama_scalar t);
+
+llama_status fail(llama_status s, const std::string& msg);
+void clear_error();
+
+// Validates `map` for record `rec` and deep-copies it.
+llama_status copy_mapping(const Rec& rec, const llama_mapping* map, MapDesc& out, int depth = 0);
+uint32_t blob_count(const Rec& rec, const MapDesc& m);
+uint64_t blob_size(const Rec& rec, const MapDesc& m, uint64_t n, uint32_t b);
+// Mapped bytes of all records (excludes AoS alignment and AoSoA padding; bit
+// streams count ceil(n * B / 8) per field).
+uint64_t mapped_bytes(const Rec& rec, const MapDesc& m, uint64_t n);
+
+}  // namespace lm
+
+struct llama_view {
+  lm::Rec rec;
+  lm::MapDesc map;
+  uint32_t rank = 1;
+  uint64_t extents[8] = {0};
+  uint64_t n = 0;
+  llama_index_type index_type = LLAMA_IDX_I64;
+  std::vector<void*> blobs;
+  std::vector<uint64_t> blob_bytes;  // bytes the mapping uses per blob
+};
+
+namespace lm {
+
+enum PlanKind : uint32_t { PK_RAW = 0, PK_CONV = 1, PK_PACK = 2, PK_UNPACK = 3 };
+
+struct Plan {
+  PlanKind kind = PK_RAW;
+  uint32_t unit = 0;
+  uint32_t grid = 0;
+  uint32_t lds = 0;
+  uint64_t alg_bytes = 0;  // mapped bytes read + mapped bytes written
+  uint64_t ntiles = 0;
+  TileArgs args{};
+};
+
+// Builds the device description of a view.  UNSUPPORTED when the tile
+// engine does not cover the mapping.
+llama_status make_side(const llama_view* v, Side& s, llama_scalar& user_t, llama_scalar& stored_t);
+
+// Tile-size granule (records) for a pair of sides: a multiple of 128 and of
+// every AoSoA lane count.
+uint64_t tile_granule(const Side& s, const Side& d);
+uint32_t tile_lds_bytes(const Side& s, uint32_t tile);
+
+llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama_launch_params* p,
+                       Plan& plan);
+llama_status launch_plan(const Plan& plan, hipStream_t st);
+
+Div make_div(uint32_t d);
+
+}  // namespace lm

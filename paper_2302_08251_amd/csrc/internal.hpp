@@ -1,0 +1,87 @@
+// Internal descriptors shared by the host runtime and the HIP kernels.
+//
+// A copy moves the records of a tile [i0, i0 + nt) between two "sides".  A
+// side is the structural form of a mapping after Bytesplit and ChangeType
+// have been resolved:
+//   LY_AOS     one segment of nt*S bytes (record-major)
+//   LY_PLANAR  one segment per storage column (SoA single/multi blob)
+//   LY_AOSOA   one segment of ceil(nt/L)*L*S bytes (blocks of L records)
+//   LY_STREAM  one LSB-first bit stream per field (BitPacked*SoA)
+// A storage column is a leaf field (cs = element size), or one byte of a
+// leaf when the mapping is a Bytesplit (cs = 1, Sec. 3 Bytesplit).
+#pragma once
+#include <stdint.h>
+
+#include "../../include/llama_mi.h"
+
+namespace lm {
+
+constexpr uint32_t kMaxFields = 64;
+constexpr uint32_t kMaxCols = 64;
+constexpr uint32_t kThreads = 256;            // threads per workgroup of the tile kernels
+constexpr uint32_t kMaxTileLds = 64 * 1024;   // LDS bytes per tile
+
+enum Layout : uint32_t { LY_AOS = 0, LY_PLANAR = 1, LY_AOSOA = 2, LY_STREAM = 3 };
+
+// How a side's stored element relates to the user value.
+enum ValueKind : uint32_t {
+  VK_RAW = 0,    // stored bits are the user bits
+  VK_CONV = 1,   // ChangeType: stored type differs from the user type
+  VK_INT = 2,    // BitPackedIntSoA code
+  VK_FLOAT = 3,  // BitPackedFloatSoA code
+};
+
+// Exact x / d for x * d < 2^32: q = (d power of two) ? x >> sh : umulhi(x, m),
+// m = ceil(2^32 / d).
+struct Div {
+  uint32_t d, m, sh, pow2;
+};
+
+struct Side {
+  uint32_t layout;     // Layout
+  uint32_t vkind;      // ValueKind
+  uint32_t cs;         // storage column size in bytes (1, 2, 4, 8)
+  uint32_t log2cs;
+  uint32_t ncols;      // storage columns (fields, or bytes of the record for Bytesplit)
+  uint32_t rec_bytes;  // S: bytes of one stored record (ncols * cs)
+  uint32_t es;         // stored element bytes (user size for RAW, storage size for CONV)
+  uint32_t lanes;      // AoSoA L
+  uint32_t mb;         // planar: 1 = one blob per column
+  uint32_t bits;       // stream: code bits (1..32)
+  uint32_t exp_bits, man_bits;
+  uint32_t is_signed;  // VK_INT: sign-extend on decode
+  uint32_t lds_stride; // planar / stream: LDS bytes per column or field plane
+  uint32_t n_mod16;    // n mod 16 (phase of single-blob planes)
+  uint32_t pad0;
+  uint64_t n;          // records
+  uint64_t blob_size;  // bytes the mapping uses in each blob (all blobs of a side are equal)
+  Div div_S;           // S
+  Div div_LS;          // L * S
+  Div div_Lcs;         // L * cs
+  Div div_L;           // L
+  Div div_B;           // stream code bits
+  const void* blob[kMaxCols];
+};
+
+// Conversions between the two sides' elements.
+enum Conv : uint32_t {
+  CV_NONE = 0,
+  CV_F64_F32 = 1,  // narrowing, round to nearest even
+  CV_F32_F64 = 2,  // widening, exact
+};
+
+// Bit-packed codecs by user element type.
+enum Codec : uint32_t {
+  CD_U8 = 0, CD_I8, CD_U16, CD_I16, CD_U32, CD_I32, CD_U64, CD_I64, CD_F32, CD_F64,
+};
+
+struct TileArgs {
+  Side src;
+  Side dst;
+  uint32_t tile;        // records per tile
+  uint32_t ntiles_lo;   // number of tiles (low 32 bits; tiles < 2^32)
+  uint32_t conv;        // Conv
+  uint32_t codec;       // Codec (pack / unpack)
+};
+
+}  // namespace lm

@@ -1,0 +1,538 @@
+// Tile engine for layout-aware copy, ChangeType conversion and bit packing
+// on gfx950 (LLAMA, arXiv 2302.08251: layout-aware copy Sec. 1, computed
+// mappings Sec. 3, AoS / SoA / AoSoA Sec. 5).
+//
+// One workgroup moves one tile of records [i0, i0 + nt):
+//   Phase A  the source side's segments for the tile are copied verbatim into
+//            LDS with direct buffer->LDS 128-bit loads (one 1 KiB group of 64
+//            lanes per wave instruction, contiguous in HBM).
+//   Phase B  each lane owns a 16-byte chunk of a destination segment (so the
+//            store is one coalesced 128-bit buffer store), inverts the
+//            destination mapping for every unit of the chunk to (record,
+//            byte of record), and gathers that unit from LDS through the
+//            source mapping's tile-local address function.
+// All global accesses go through buffer resources whose range is the blob
+// the mapping uses, so an access outside the blob is dropped by hardware.
+// Per-lane offsets are 32-bit; only the per-segment scalar base is 64-bit.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace lm {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) void lds_void;
+
+constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit format, gfx9 family
+
+__device__ __forceinline__ uint32_t wave_id() {
+  return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
+__device__ __forceinline__ uint32_t num_waves() { return blockDim.x >> 6; }
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t x, const Div& d) {
+  return d.pow2 ? (x >> d.sh) : __umulhi(x, d.m);
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint64_t bytes) {
+  const uint32_t nr = bytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)nr, kRsrcWord3);
+}
+
+// ---------------------------------------------------------------------------
+// Segment geometry of one side for a tile
+// ---------------------------------------------------------------------------
+
+struct SegGeo {
+  uint32_t nseg;  // segments of the tile
+  uint32_t len;   // bytes per segment (equal for all segments)
+};
+
+__device__ __forceinline__ SegGeo seg_geo(const Side& s, uint32_t nt) {
+  switch (s.layout) {
+    case LY_AOS: return {1u, nt * s.rec_bytes};
+    case LY_AOSOA: return {1u, fdiv(nt + s.lanes - 1, s.div_L) * s.lanes * s.rec_bytes};
+    case LY_PLANAR: return {s.ncols, nt * s.cs};
+    default: return {s.ncols, ((nt * s.bits + 31u) >> 5) * 4u};
+  }
+}
+
+// Byte offset, within its blob, where segment `seg` of the tile at i0 starts.
+__device__ __forceinline__ uint64_t seg_start(const Side& s, uint32_t seg, uint64_t i0) {
+  switch (s.layout) {
+    case LY_AOS:
+    case LY_AOSOA: return i0 * s.rec_bytes;
+    case LY_PLANAR: return (s.mb ? 0ull : s.n * s.cs * seg) + i0 * s.cs;
+    default: return (i0 * s.bits) >> 3;
+  }
+}
+
+__device__ __forceinline__ const void* seg_blob(const Side& s, uint32_t seg) {
+  const bool per_col = s.layout == LY_STREAM || (s.layout == LY_PLANAR && s.mb);
+  return per_col ? s.blob[seg] : s.blob[0];
+}
+
+// LDS offset of segment `seg`'s allocation.  The data starts at
+// seg_lds + (start mod 16), so a 16-byte aligned global chunk lands on a
+// 16-byte aligned LDS chunk.
+__device__ __forceinline__ uint32_t seg_lds(const Side& s, uint32_t seg) {
+  return (s.layout == LY_PLANAR || s.layout == LY_STREAM) ? seg * s.lds_stride : 0u;
+}
+
+// Start phase (mod 16) of planar column c of a single-blob side.
+__device__ __forceinline__ uint32_t planar_phase(const Side& s, uint32_t c) {
+  return s.mb ? 0u : ((s.n_mod16 * s.cs * c) & 15u);
+}
+
+// ---------------------------------------------------------------------------
+// Phase A: source tile -> LDS, verbatim
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void load_tile(const Side& s, uint64_t i0, uint32_t nt, uint8_t* lds) {
+  const SegGeo g = seg_geo(s, nt);
+  const uint32_t w = wave_id(), nw = num_waves(), lane = lane_id();
+  const uint32_t gps = (g.len + 15u + 1023u) >> 10;  // groups of 64 chunks per segment
+  const uint32_t items = g.nseg * gps;
+  for (uint32_t it = w; it < items; it += nw) {
+    const uint32_t seg = it / gps;
+    const uint32_t grp = it - seg * gps;
+    const uint64_t start = seg_start(s, seg, i0);
+    const uint32_t phase = (uint32_t)start & 15u;
+    const uint64_t abase = start - phase;
+    const auto rs = make_rsrc((const uint8_t*)seg_blob(s, seg) + abase, s.blob_size - abase);
+    const uint32_t chunk = grp * 64u + lane;
+    if (chunk * 16u < phase + g.len) {
+      if (abase + chunk * 16ull + 16ull <= s.blob_size) {
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void*)(lds + seg_lds(s, seg) + grp * 1024u),
+                                                 16, chunk * 16u, 0, 0, 0);
+      } else {
+        // The chunk crosses the end of the blob.  Buffer range checks work on
+        // whole dwords, so a blob size that is not a multiple of 4 would zero
+        // the last bytes: fetch this chunk byte by byte instead.
+        uint8_t* out = lds + seg_lds(s, seg) + chunk * 16u;
+        const uint64_t left = s.blob_size - (abase + chunk * 16ull);
+        for (uint32_t k = 0; k < 16u && k < left; ++k)
+          out[k] = __builtin_amdgcn_raw_buffer_load_b8(rs, chunk * 16u + k, 0, 0);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void wait_tile_loads() {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Mapping functions on tile-local coordinates
+// ---------------------------------------------------------------------------
+
+// Destination inverse: byte x of destination segment `seg` holds byte b of
+// the stored record image of tile-local record r.
+template <int DL>
+__device__ __forceinline__ void dst_inv(const Side& d, uint32_t seg, uint32_t x, uint32_t& r,
+                                        uint32_t& b) {
+  if constexpr (DL == LY_AOS) {
+    r = fdiv(x, d.div_S);
+    b = x - r * d.rec_bytes;
+  } else if constexpr (DL == LY_PLANAR) {
+    r = x >> d.log2cs;
+    b = seg * d.cs + (x & (d.cs - 1u));
+  } else {  // LY_AOSOA: block, column, lane, byte
+    const uint32_t blk = fdiv(x, d.div_LS);
+    const uint32_t y = x - blk * (d.lanes * d.rec_bytes);
+    const uint32_t c = fdiv(y, d.div_Lcs);
+    const uint32_t z = y - c * (d.lanes * d.cs);
+    r = blk * d.lanes + (z >> d.log2cs);
+    b = c * d.cs + (z & (d.cs - 1u));
+  }
+}
+
+// Source forward: LDS offset of byte b of the stored record image of
+// tile-local record r.
+template <int SL>
+__device__ __forceinline__ uint32_t src_addr(const Side& s, uint32_t r, uint32_t b) {
+  if constexpr (SL == LY_AOS) {
+    return r * s.rec_bytes + b;
+  } else if constexpr (SL == LY_PLANAR) {
+    const uint32_t c = b >> s.log2cs;
+    return c * s.lds_stride + planar_phase(s, c) + r * s.cs + (b & (s.cs - 1u));
+  } else {  // LY_AOSOA
+    const uint32_t c = b >> s.log2cs;
+    const uint32_t blk = fdiv(r, s.div_L);
+    const uint32_t lane = r - blk * s.lanes;
+    return blk * (s.lanes * s.rec_bytes) + c * (s.lanes * s.cs) + lane * s.cs + (b & (s.cs - 1u));
+  }
+}
+
+template <int U>
+__device__ __forceinline__ uint64_t lds_read(const uint8_t* lds, uint32_t a) {
+  if constexpr (U == 1) return lds[a];
+  else if constexpr (U == 2) return *(const uint16_t*)(lds + a);
+  else if constexpr (U == 4) return *(const uint32_t*)(lds + a);
+  else return *(const uint64_t*)(lds + a);
+}
+
+// Store `nunits` units of U bytes of a 16-byte chunk; full chunks go out as
+// one 128-bit store, partial ones unit by unit.
+template <int U>
+__device__ __forceinline__ void store_chunk(__amdgpu_buffer_rsrc_t rs, uint32_t off, const uint32_t (&w)[4],
+                                            uint32_t valid, uint32_t full_mask) {
+  if (valid == full_mask) {
+    u32x4 v = {w[0], w[1], w[2], w[3]};
+    __builtin_amdgcn_raw_buffer_store_b128(v, rs, off, 0, 0);
+    return;
+  }
+#pragma unroll
+  for (int t = 0; t < 16 / U; ++t) {
+    if (!((valid >> t) & 1u)) continue;
+    const uint32_t byte = t * U;
+    if constexpr (U == 1) {
+      __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(w[byte >> 2] >> ((byte & 3u) * 8u)), rs, off + byte, 0, 0);
+    } else if constexpr (U == 2) {
+      __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(w[byte >> 2] >> ((byte & 3u) * 8u)), rs, off + byte, 0, 0);
+    } else if constexpr (U == 4) {
+      __builtin_amdgcn_raw_buffer_store_b32(w[byte >> 2], rs, off + byte, 0, 0);
+    } else {
+      u32x2 v = {w[byte >> 2], w[(byte >> 2) + 1]};
+      __builtin_amdgcn_raw_buffer_store_b64(v, rs, off + byte, 0, 0);
+    }
+  }
+}
+
+template <int U>
+__device__ __forceinline__ void put_unit(uint32_t (&w)[4], int t, uint64_t v) {
+  if constexpr (U == 8) {
+    w[2 * t] = (uint32_t)v;
+    w[2 * t + 1] = (uint32_t)(v >> 32);
+  } else if constexpr (U == 4) {
+    w[t] = (uint32_t)v;
+  } else {
+    const uint32_t byte = t * U;
+    w[byte >> 2] |= ((uint32_t)v & ((1u << (8 * U)) - 1u)) << ((byte & 3u) * 8u);
+  }
+}
+
+// Iterates over the 16-byte chunks of the destination segments of a tile,
+// one group of 64 chunks per wave at a time; `body(rs, seg, chunk, x0, len)`
+// handles one chunk whose first byte is segment byte x0 (negative for the
+// bytes before a misaligned segment start).
+template <typename Body>
+__device__ __forceinline__ void for_dst_chunks(const Side& d, uint64_t i0, uint32_t nt, Body&& body) {
+  const SegGeo g = seg_geo(d, nt);
+  const uint32_t w = wave_id(), nw = num_waves(), lane = lane_id();
+  const uint32_t gps = (g.len + 15u + 1023u) >> 10;
+  const uint32_t items = g.nseg * gps;
+  for (uint32_t it = w; it < items; it += nw) {
+    const uint32_t seg = it / gps;
+    const uint32_t grp = it - seg * gps;
+    const uint64_t start = seg_start(d, seg, i0);
+    const uint32_t phase = (uint32_t)start & 15u;
+    const uint64_t abase = start - phase;
+    const auto rs = make_rsrc((const uint8_t*)seg_blob(d, seg) + abase, d.blob_size - abase);
+    const uint32_t chunk = grp * 64u + lane;
+    const int x0 = (int)(chunk * 16u) - (int)phase;
+    if (x0 < (int)g.len) body(rs, seg, chunk * 16u, x0, g.len);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Phase B, raw copy: units of U = min(source column, destination column) bytes
+// ---------------------------------------------------------------------------
+
+template <int U, int DL, int SL>
+__device__ __forceinline__ void store_raw(const Side& s, const Side& d, uint64_t i0, uint32_t nt,
+                                          const uint8_t* lds) {
+  constexpr int NU = 16 / U;
+  constexpr uint32_t FULL = (1u << NU) - 1u;
+  for_dst_chunks(d, i0, nt, [&](__amdgpu_buffer_rsrc_t rs, uint32_t seg, uint32_t off, int x0, uint32_t len) {
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+    uint32_t valid = 0;
+#pragma unroll
+    for (int t = 0; t < NU; ++t) {
+      const int x = x0 + t * U;
+      bool ok = x >= 0 && x < (int)len;
+      uint32_t r, b;
+      dst_inv<DL>(d, seg, ok ? (uint32_t)x : 0u, r, b);
+      ok = ok && r < nt;
+      if (ok) put_unit<U>(w, t, lds_read<U>(lds, src_addr<SL>(s, r, b)));
+      valid |= (uint32_t)ok << t;
+    }
+    store_chunk<U>(rs, off, w, valid, FULL);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Element access for conversions and codecs
+// ---------------------------------------------------------------------------
+
+// Stored element of field f (ES bytes) of tile-local record r from the source
+// tile in LDS; a Bytesplit source (cs = 1) is gathered byte by byte.
+template <int ES, int SL>
+__device__ __forceinline__ uint64_t fetch_elem(const Side& s, const uint8_t* lds, uint32_t r, uint32_t f) {
+  if (s.cs == (uint32_t)ES) return lds_read<ES>(lds, src_addr<SL>(s, r, f * ES));
+  uint64_t v = 0;
+#pragma unroll
+  for (int k = 0; k < ES; ++k) v |= (uint64_t)lds[src_addr<SL>(s, r, f * ES + k)] << (8 * k);
+  return v;
+}
+
+// ChangeType conversions (Sec. 3): the hardware conversion instructions,
+// with NaN made quiet and keeping its top payload bits.
+__device__ __forceinline__ uint32_t cvt_f64_f32(uint64_t x) {
+  const float f = (float)__builtin_bit_cast(double, x);  // v_cvt_f32_f64, round to nearest even
+  const uint32_t r = __builtin_bit_cast(uint32_t, f);
+  const bool nan = (x & 0x7FFFFFFFFFFFFFFFull) > 0x7FF0000000000000ull;
+  const uint32_t rn = ((uint32_t)(x >> 32) & 0x80000000u) | 0x7FC00000u | (uint32_t)((x >> 29) & 0x7FFFFFu);
+  return nan ? rn : r;
+}
+
+__device__ __forceinline__ uint64_t cvt_f32_f64(uint32_t x) {
+  const double d = (double)__builtin_bit_cast(float, x);  // v_cvt_f64_f32, exact
+  const uint64_t r = __builtin_bit_cast(uint64_t, d);
+  const bool nan = (x & 0x7FFFFFFFu) > 0x7F800000u;
+  const uint64_t rn = ((uint64_t)(x >> 31) << 63) | 0x7FF8000000000000ull | ((uint64_t)(x & 0x7FFFFFu) << 29);
+  return nan ? rn : r;
+}
+
+// BitPackedFloatSoA codes (Sec. 3): [sign | E | M], bias 2^(E-1)-1,
+// mantissa truncated, overflow -> Inf, gradual underflow, NaN kept quiet.
+__device__ __forceinline__ uint32_t enc_f32(uint32_t x, uint32_t E, uint32_t M) {
+  const uint32_t sh = 23u - M;
+  const uint32_t bias = (1u << (E - 1u)) - 1u;
+  const uint32_t emin = 128u - bias;   // smallest source exponent field with a target normal
+  const uint32_t emaxf = 127u + bias;  // largest source exponent field that stays finite
+  const uint32_t inf_code = ((1u << E) - 1u) << M;
+  const uint32_t ax = x & 0x7FFFFFFFu, e = ax >> 23, m = ax & 0x7FFFFFu;
+  const uint32_t c_norm = ((e - emin + 1u) << M) | (m >> sh);
+  const uint32_t sig = e ? (m | 0x800000u) : m;
+  const uint32_t dsh = emin - (e ? e : 1u) + sh;
+  const uint32_t c_sub = dsh < 32u ? (sig >> dsh) : 0u;
+  const uint32_t quiet = M ? (1u << (M - 1u)) : 0u;
+  const uint32_t c_inf = inf_code | ((ax > 0x7F800000u && M) ? ((m >> sh) | quiet) : 0u);
+  const uint32_t c = e > emaxf ? c_inf : (e >= emin ? c_norm : c_sub);
+  return c | ((x >> 31) << (E + M));
+}
+
+__device__ __forceinline__ uint32_t dec_f32(uint32_t c, uint32_t E, uint32_t M) {
+  const uint32_t sh = 23u - M;
+  const uint32_t bias = (1u << (E - 1u)) - 1u;
+  const uint32_t emax = (1u << E) - 1u;
+  const uint32_t e = (c >> M) & emax, m = c & ((1u << M) - 1u);
+  const uint32_t sign = ((c >> (E + M)) & 1u) << 31;
+  uint32_t r;
+  if (e == emax) {
+    r = 0x7F800000u | (m << sh);
+  } else if (e) {
+    r = ((e + 127u - bias) << 23) | (m << sh);
+  } else if (m == 0u) {
+    r = 0u;
+  } else {  // target subnormal m * 2^(1 - bias - M)
+    const int p = 31 - __builtin_clz(m);
+    const int u = 1 - (int)bias - (int)M + p;
+    r = u >= -126 ? (((uint32_t)(u + 127) << 23) | ((m ^ (1u << p)) << (23 - p))) : (m << sh);
+  }
+  return r | sign;
+}
+
+__device__ __forceinline__ uint32_t enc_f64(uint64_t x, uint32_t E, uint32_t M) {
+  const uint32_t sh = 52u - M;
+  const uint32_t bias = (1u << (E - 1u)) - 1u;
+  const uint32_t emin = 1024u - bias;
+  const uint32_t emaxf = 1023u + bias;
+  const uint32_t inf_code = ((1u << E) - 1u) << M;
+  const uint64_t ax = x & 0x7FFFFFFFFFFFFFFFull, m = ax & 0xFFFFFFFFFFFFFull;
+  const uint32_t e = (uint32_t)(ax >> 52);
+  const uint32_t c_norm = ((e - emin + 1u) << M) | (uint32_t)(m >> sh);
+  const uint64_t sig = e ? (m | 0x10000000000000ull) : m;
+  const uint32_t dsh = emin - (e ? e : 1u) + sh;
+  const uint32_t c_sub = dsh < 64u ? (uint32_t)(sig >> dsh) : 0u;
+  const uint32_t quiet = M ? (1u << (M - 1u)) : 0u;
+  const uint32_t c_inf = inf_code | ((ax > 0x7FF0000000000000ull && M) ? ((uint32_t)(m >> sh) | quiet) : 0u);
+  const uint32_t c = e > emaxf ? c_inf : (e >= emin ? c_norm : c_sub);
+  return c | ((uint32_t)(x >> 63) << (E + M));
+}
+
+__device__ __forceinline__ uint64_t dec_f64(uint32_t c, uint32_t E, uint32_t M) {
+  const uint32_t sh = 52u - M;
+  const uint32_t bias = (1u << (E - 1u)) - 1u;
+  const uint32_t emax = (1u << E) - 1u;
+  const uint32_t e = (c >> M) & emax, m = c & ((1u << M) - 1u);
+  const uint64_t sign = (uint64_t)((c >> (E + M)) & 1u) << 63;
+  uint64_t r;
+  if (e == emax) {
+    r = 0x7FF0000000000000ull | ((uint64_t)m << sh);
+  } else if (e) {
+    r = ((uint64_t)(e + 1023u - bias) << 52) | ((uint64_t)m << sh);
+  } else if (m == 0u) {
+    r = 0ull;
+  } else {
+    const int p = 31 - __builtin_clz(m);
+    const int u = 1 - (int)bias - (int)M + p;
+    r = u >= -1022 ? (((uint64_t)(u + 1023) << 52) | ((uint64_t)(m ^ (1u << p)) << (52 - p)))
+                   : ((uint64_t)m << sh);
+  }
+  return r | sign;
+}
+
+// user element -> code (pack)
+template <int CODEC>
+__device__ __forceinline__ uint32_t encode(uint64_t v, const Side& d) {
+  if constexpr (CODEC == CD_F32) return enc_f32((uint32_t)v, d.exp_bits, d.man_bits);
+  else if constexpr (CODEC == CD_F64) return enc_f64(v, d.exp_bits, d.man_bits);
+  else return (uint32_t)v & (d.bits >= 32u ? 0xFFFFFFFFu : ((1u << d.bits) - 1u));
+}
+
+// code -> user element bits (unpack)
+template <int CODEC>
+__device__ __forceinline__ uint64_t decode(uint32_t c, const Side& s) {
+  if constexpr (CODEC == CD_F32) return dec_f32(c, s.exp_bits, s.man_bits);
+  else if constexpr (CODEC == CD_F64) return dec_f64(c, s.exp_bits, s.man_bits);
+  else {
+    constexpr bool SGN = CODEC == CD_I8 || CODEC == CD_I16 || CODEC == CD_I32 || CODEC == CD_I64;
+    if constexpr (SGN) {
+      const int32_t v = s.bits >= 32u ? (int32_t)c : ((int32_t)(c << (32u - s.bits)) >> (32u - s.bits));
+      return (uint64_t)(int64_t)v;
+    } else {
+      return (uint64_t)c;
+    }
+  }
+}
+
+template <int CODEC>
+struct CodecInfo {
+  static constexpr int ES = (CODEC == CD_U8 || CODEC == CD_I8) ? 1
+                          : (CODEC == CD_U16 || CODEC == CD_I16) ? 2
+                          : (CODEC == CD_U32 || CODEC == CD_I32 || CODEC == CD_F32) ? 4 : 8;
+};
+
+// code of tile-local value r from an LDS bit-stream plane (B <= 32)
+__device__ __forceinline__ uint32_t stream_code(const uint8_t* plane, uint32_t r, uint32_t B) {
+  const uint32_t p = r * B;
+  const uint32_t* wp = (const uint32_t*)plane + (p >> 5);
+  const uint32_t lo = wp[0], hi = wp[1];
+  const uint32_t v = __builtin_amdgcn_alignbit(hi, lo, p & 31u);
+  return B >= 32u ? v : (v & ((1u << B) - 1u));
+}
+
+// ---------------------------------------------------------------------------
+// Phase B, ChangeType conversion.  Units are destination storage bytes of
+// U = (destination column size); the source element is read whole.
+// ---------------------------------------------------------------------------
+
+template <int CONV>
+struct ConvInfo {
+  static constexpr int ES_SRC = CONV == CV_F64_F32 ? 8 : 4;
+  static constexpr int ES_DST = CONV == CV_F64_F32 ? 4 : 8;
+};
+
+template <int CONV>
+__device__ __forceinline__ uint64_t convert(uint64_t v) {
+  if constexpr (CONV == CV_F64_F32) return cvt_f64_f32(v);
+  else return cvt_f32_f64((uint32_t)v);
+}
+
+template <int CONV, int U, int DL, int SL>
+__device__ __forceinline__ void store_conv(const Side& s, const Side& d, uint64_t i0, uint32_t nt,
+                                           const uint8_t* lds) {
+  constexpr int NU = 16 / U;
+  constexpr uint32_t FULL = (1u << NU) - 1u;
+  constexpr int ESS = ConvInfo<CONV>::ES_SRC, ESD = ConvInfo<CONV>::ES_DST;
+  constexpr int LOG_ESD = ESD == 8 ? 3 : 2;
+  for_dst_chunks(d, i0, nt, [&](__amdgpu_buffer_rsrc_t rs, uint32_t seg, uint32_t off, int x0, uint32_t len) {
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+    uint32_t valid = 0;
+#pragma unroll
+    for (int t = 0; t < NU; ++t) {
+      const int x = x0 + t * U;
+      bool ok = x >= 0 && x < (int)len;
+      uint32_t r, b;
+      dst_inv<DL>(d, seg, ok ? (uint32_t)x : 0u, r, b);
+      ok = ok && r < nt;
+      if (ok) {
+        const uint64_t v = convert<CONV>(fetch_elem<ESS, SL>(s, lds, r, b >> LOG_ESD));
+        const uint32_t k = b & (ESD - 1);
+        put_unit<U>(w, t, U == ESD ? v : ((v >> (8u * k)) & ((1ull << (8 * U)) - 1ull)));
+      }
+      valid |= (uint32_t)ok << t;
+    }
+    store_chunk<U>(rs, off, w, valid, FULL);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Phase B, pack into bit streams: each lane assembles four 32-bit words of
+// one field's stream from the values whose bits they hold.
+// ---------------------------------------------------------------------------
+
+template <int CODEC, int SL>
+__device__ __forceinline__ void store_pack(const Side& s, const Side& d, uint64_t i0, uint32_t nt,
+                                           const uint8_t* lds) {
+  constexpr int ES = CodecInfo<CODEC>::ES;
+  const uint32_t B = d.bits;
+  for_dst_chunks(d, i0, nt, [&](__amdgpu_buffer_rsrc_t rs, uint32_t f, uint32_t off, int x0, uint32_t len) {
+    uint32_t w[4];
+    uint32_t valid = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t wi = (uint32_t)x0 / 4u + q;  // tile-local word index (segments start 16-aligned)
+      const bool ok = wi * 4u < len;
+      uint32_t acc = 0;
+      if (ok) {
+        const uint32_t bit0 = wi * 32u;
+        uint32_t r = fdiv(bit0, d.div_B);
+        const uint32_t first = bit0 - r * B;
+        acc = encode<CODEC>(fetch_elem<ES, SL>(s, lds, r, f), d) >> first;
+        uint32_t nb = B - first;
+        ++r;
+        while (nb < 32u && r < nt) {
+          acc |= encode<CODEC>(fetch_elem<ES, SL>(s, lds, r, f), d) << nb;
+          nb += B;
+          ++r;
+        }
+      }
+      w[q] = acc;
+      valid |= (uint32_t)ok << q;
+    }
+    store_chunk<4>(rs, off, w, valid, 0xFu);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Phase B, unpack from bit streams into a physical layout
+// ---------------------------------------------------------------------------
+
+template <int CODEC, int U, int DL>
+__device__ __forceinline__ void store_unpack(const Side& s, const Side& d, uint64_t i0, uint32_t nt,
+                                             const uint8_t* lds) {
+  constexpr int NU = 16 / U;
+  constexpr uint32_t FULL = (1u << NU) - 1u;
+  constexpr int ES = CodecInfo<CODEC>::ES;
+  constexpr int LOG_ES = ES == 8 ? 3 : ES == 4 ? 2 : ES == 2 ? 1 : 0;
+  const uint32_t B = s.bits;
+  for_dst_chunks(d, i0, nt, [&](__amdgpu_buffer_rsrc_t rs, uint32_t seg, uint32_t off, int x0, uint32_t len) {
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+    uint32_t valid = 0;
+#pragma unroll
+    for (int t = 0; t < NU; ++t) {
+      const int x = x0 + t * U;
+      bool ok = x >= 0 && x < (int)len;
+      uint32_t r, b;
+      dst_inv<DL>(d, seg, ok ? (uint32_t)x : 0u, r, b);
+      ok = ok && r < nt;
+      if (ok) {
+        const uint32_t f = b >> LOG_ES;
+        const uint64_t v = decode<CODEC>(stream_code(lds + f * s.lds_stride, r, B), s);
+        const uint32_t k = b & (ES - 1);
+        put_unit<U>(w, t, U == ES ? v : ((v >> (8u * k)) & ((1ull << (8 * U)) - 1ull)));
+      }
+      valid |= (uint32_t)ok << t;
+    }
+    store_chunk<U>(rs, off, w, valid, FULL);
+  });
+}
+
+}  // namespace lm

@@ -1,0 +1,101 @@
+"""GPU n-body consumer (Sec. 5: update writes velocities from all positions,
+then the move phase advances positions) against the FP64 oracle started from
+the same decoded initial state.  The FP32 form (ChangeType f64 -> f32 over
+AoSoA-32) is held to a normwise relative error <= 1e-5 on positions and
+velocities; the e8m15 bit-packed form stores 15 mantissa bits, so its error
+is reported and only bounded loosely.  The bitwise FP32 result is not unique
+(summation order), so no test compares it bit for bit (parity unpinned)."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import F64x7, download, gpu_view, say
+
+import paper_2302_08251_amd as lm
+from paper_2302_08251_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+EPS2, DT = 0.01, 1e-4
+CT_AOSOA32 = {"kind": "changetype", "stored": ["f32"] * 7, "inner": {"kind": "aosoa", "lanes": 32}}
+E8M15 = {"kind": "bitpack_float", "exp": 8, "man": 15}
+
+
+def state(planes):
+    pos = np.stack(planes[0:3], axis=1).astype(np.float64)
+    vel = np.stack(planes[3:6], axis=1).astype(np.float64)
+    return pos, vel, planes[6].astype(np.float64)
+
+
+def run(rec, spec, n, steps, seed=0):
+    """GPU steps through the view; returns (gpu pos, vel), (oracle pos, vel), initial state."""
+    init = synth.particles(n, seed, dtype=np.float64 if rec[0] == "f64" else np.float32)
+    host = oracle.store_planes(rec, spec, init)
+    pos0, vel0, mass = state(oracle.load_planes(rec, spec, host, n))
+    v = gpu_view(rec, spec, n, host)
+    lm.nbody_step(v, steps, DT, EPS2)
+    gp, gv, gm = state(oracle.load_planes(rec, spec, download(v), n))
+    assert np.array_equal(gm, mass), "the update must not change masses"
+    rp, rv = oracle.nbody(pos0, vel0, mass, steps, DT, EPS2)
+    return (gp, gv), (rp, rv), (pos0, vel0, mass), v
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("spec", [
+    {"kind": "aos"}, {"kind": "soa_mb"}, {"kind": "soa_sb"}, {"kind": "aosoa", "lanes": 32},
+    {"kind": "bytesplit", "inner": {"kind": "soa_sb"}}], ids=lambda s: s["kind"] + str(s.get("lanes", "")))
+def test_f32_physical_small(spec):
+    (gp, gv), (rp, rv), _, _ = run(["f32"] * 7, spec, 1000, 3)
+    say("f32", spec, rel(gp, rp), rel(gv, rv))
+    assert rel(gp, rp) <= 1e-6 and rel(gv, rv) <= 1e-5
+
+
+@pytest.mark.parametrize("n", [1, 255, 257, 3000])
+def test_ragged_sizes_ct_aosoa32(n):
+    (gp, gv), (rp, rv), _, _ = run(F64x7, CT_AOSOA32, n, 2)
+    say("ragged", n, rel(gp, rp), rel(gv, rv))
+    assert rel(gp, rp) <= 1e-6 and rel(gv, rv) <= 1e-5
+
+
+@pytest.mark.parametrize("n", [300, 4096])
+def test_e8m15_small(n):
+    (gp, gv), (rp, rv), _, _ = run(F64x7, E8M15, n, 2)
+    say("e8m15", n, rel(gp, rp), rel(gv, rv))
+    assert rel(gp, rp) <= 1e-4 and rel(gv, rv) <= 1e-3
+
+
+def test_cfg5_f32_form_full_size():
+    """N = 65536, 10 steps, positions and velocities within 1e-5 of FP64 (after step 1
+    and after step 10); energy drift reported."""
+    n = 65536
+    for steps in (1, 10):
+        (gp, gv), (rp, rv), (p0, v0, m), view = run(F64x7, CT_AOSOA32, n, steps)
+        ex, ev = rel(gp, rp), rel(gv, rv)
+        say("cfg5 ChangeType(f64->f32, AoSoA-32) steps=%d pos %.3g vel %.3g" % (steps, ex, ev))
+        assert ex <= 1e-5 and ev <= 1e-5
+    e_gpu = lm.nbody_energy(view, EPS2)
+    e_ref = oracle.energy(gp, gv, m, EPS2)
+    e0 = oracle.energy(p0, v0, m, EPS2)
+    say("energy gpu %.12g oracle-of-gpu-state %.12g drift %.3g" % (e_gpu, e_ref, (e_gpu - e0) / abs(e0)))
+    assert abs(e_gpu - e_ref) <= 1e-10 * abs(e_ref)
+
+
+def test_cfg5_e8m15_form_full_size():
+    n = 65536
+    (gp, gv), (rp, rv), _, _ = run(F64x7, E8M15, n, 10)
+    ex, ev = rel(gp, rp), rel(gv, rv)
+    say("cfg5 BitPackedFloat e8m15 steps=10 pos %.3g vel %.3g (reported)" % (ex, ev))
+    assert ex <= 1e-3 and ev <= 1e-2
+
+
+def test_energy_matches_oracle():
+    n = 2000
+    init = synth.particles(n, 5, dtype=np.float64)
+    host = oracle.store_planes(F64x7, CT_AOSOA32, init)
+    p, v, m = state(oracle.load_planes(F64x7, CT_AOSOA32, host, n))
+    view = gpu_view(F64x7, CT_AOSOA32, n, host)
+    e = lm.nbody_energy(view, EPS2)
+    assert abs(e - oracle.energy(p, v, m, EPS2)) <= 1e-11 * abs(e)
