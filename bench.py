@@ -1,0 +1,396 @@
+"""Benchmark of the gfx950 layout-copy / pack library on one MI355X.
+
+One step = one pass of the layout-copy hot path over the single-view workload:
+64 Mi particle records {pos.x,pos.y,pos.z,vel.x,vel.y,vel.z,mass} of float32,
+copied once along each of the 36 ordered pairs of AoS, SoA single-blob, SoA
+multi-blob, AoSoA-32, AoSoA-64 and Bytesplit(SoA single-blob), 32-bit index
+type.  `value` is the step's algorithmic bytes (mapped bytes read + mapped
+bytes written) divided by its time, inputs resident in HBM.
+
+The same JSON line carries the other rows of the hot path measured at their
+own workloads (float/int bit packing and ChangeType on 256 Mi / 64 Mi
+elements, the 2000-view batched copy against per-view launches, and the
+all-pairs n-body step), the roofline of the dominant kernel and the CPU
+oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_PEAK_TFLOPS = 157.3        # vector FP32 (packed) peak
+METRIC = "layout-copy & pack GB/s (% of HBM peak), batched vs per-view, bit-exact"
+F32x7 = ["f32"] * 7
+LAYOUTS = {
+    "AoS": {"kind": "aos"},
+    "SoA-SB": {"kind": "soa_sb"},
+    "SoA-MB": {"kind": "soa_mb"},
+    "AoSoA-32": {"kind": "aosoa", "lanes": 32},
+    "AoSoA-64": {"kind": "aosoa", "lanes": 64},
+    "Bytesplit": {"kind": "bytesplit", "inner": {"kind": "soa_sb"}},
+}
+PAIR_ORDER = list(LAYOUTS)  # pair index p -> (src, dst) over the 30 off-diagonal pairs
+OFFDIAG = [(a, b) for a in PAIR_ORDER for b in PAIR_ORDER if a != b]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class Timer:
+    """HIP events on the current torch stream (the stream the library launches on)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+
+    def time(self, fn, reps):
+        t = self.torch
+        evs = [(t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in evs:
+            a.record()
+            fn()
+            b.record()
+        t.cuda.synchronize()
+        return [a.elapsed_time(b) for a, b in evs]  # ms
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in ("tile_engine.hpp", "kernels.hpp", "k_raw.hip", "internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2302_08251_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(alg_bytes):
+    """HBM bytes per launch from committed rocprofv3 counter runs, when they were taken
+    on the current kernel sources; otherwise None."""
+    p = os.path.join(ROOT, "profiles", "traffic_copy_cfg2.json")
+    try:
+        with open(p) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+# ------------------------------------------------------------------ cfg2: single view, 36 pairs
+
+def bench_cfg2(lm, torch, steps, warmup, n):
+    from paper_2302_08251_amd import synth
+    T = Timer(torch)
+    log("cfg2: generating %d records" % n)
+    planes = synth.particles(n, 0, dtype=np.float32)
+    mb = lm.View(F32x7, LAYOUTS["SoA-MB"], [n], index_type="i32",
+                 blobs=[torch.from_numpy(p.view(np.uint8)).cuda() for p in planes])
+    del planes
+    src = {k: lm.View(F32x7, s, [n], index_type="i32") for k, s in LAYOUTS.items()}
+    dst = {k: lm.View(F32x7, s, [n], index_type="i32") for k, s in LAYOUTS.items()}
+    for k in LAYOUTS:
+        lm.llama_copy(mb, src[k])
+    torch.cuda.synchronize()
+    # property check before timing: X -> Y -> SoA-MB reproduces the planes bit for bit
+    back = lm.View(F32x7, LAYOUTS["SoA-MB"], [n], index_type="i32")
+    for a in PAIR_ORDER:
+        for b in PAIR_ORDER:
+            lm.llama_copy(src[a], dst[b])
+            lm.llama_copy(dst[b], back)
+            torch.cuda.synchronize()
+            for f in range(7):
+                if not torch.equal(back.blobs[f][: 4 * n], mb.blobs[f][: 4 * n]):
+                    raise SystemExit("cfg2 round trip %s -> %s -> SoA-MB is not bit-exact" % (a, b))
+    alg = 2 * n * 28
+    pairs = [(a, b) for a in PAIR_ORDER for b in PAIR_ORDER]
+
+    def step():
+        for a, b in pairs:
+            lm.llama_copy(src[a], dst[b])
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    per_pair = {f"{a}->{b}": [] for a, b in pairs}
+    step_ms = []
+    for _ in range(steps):
+        ts = []
+        for a, b in pairs:
+            ms = T.time(lambda: lm.llama_copy(src[a], dst[b]), 1)[0]
+            per_pair[f"{a}->{b}"].append(ms)
+            ts.append(ms)
+        step_ms.append(sum(ts))
+    med = {k: float(np.median(v)) for k, v in per_pair.items()}
+    step_med = float(np.median(step_ms))
+    # also the end-to-end step time without per-launch events
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3 / steps
+    # device-to-device memcpy of one side's bytes: practical copy ceiling
+    a = torch.empty(n * 28, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    cp = T.time(lambda: b.copy_(a), 5)
+    memcpy_gbs = 2 * n * 28 / (np.median(cp) * 1e-3) / 1e9
+    del a, b
+    for v in list(src.values()) + list(dst.values()) + [mb, back]:
+        v.close()
+    torch.cuda.empty_cache()
+    pair_gbs = {k: alg / (v * 1e-3) / 1e9 for k, v in med.items()}
+    off = [pair_gbs[f"{a}->{b}"] for a, b in OFFDIAG]
+    return {
+        "records": n, "alg_bytes_per_pair": alg, "step_ms": step_med, "step_wall_ms": wall_ms,
+        "gbs_step": 36 * alg / (step_med * 1e-3) / 1e9,
+        "pair_gbs": {k: round(v, 1) for k, v in pair_gbs.items()},
+        "pair_ms": {k: round(v, 4) for k, v in med.items()},
+        "offdiag_min_gbs": min(off), "offdiag_max_gbs": max(off),
+        "memcpy_dtod_gbs": memcpy_gbs,
+    }
+
+
+# ------------------------------------------------------------------ cfg3: computed mappings
+
+def bench_cfg3(lm, torch, reps, n_vals, n_rec):
+    from paper_2302_08251_amd import synth
+    T = Timer(torch)
+    out = {}
+    log("cfg3: float pack/unpack on %d values" % n_vals)
+    bits = torch.from_numpy(synth.float_specials(n_vals, 0).view(np.uint8)).cuda()
+    src = lm.View(["f32"], {"kind": "soa_mb"}, [n_vals], blobs=[bits], index_type="u32")
+    back = lm.View(["f32"], {"kind": "soa_mb"}, [n_vals], index_type="u32")
+    for E, M in ((8, 7), (5, 10), (8, 15)):
+        c = lm.View(["f32"], {"kind": "bitpack_float", "exp": E, "man": M}, [n_vals], index_type="u32")
+        lm.llama_pack(src, c)
+        lm.llama_unpack(c, back)
+        alg = 4 * n_vals + (n_vals * (1 + E + M) + 7) // 8
+        tp = float(np.median(T.time(lambda: lm.llama_pack(src, c), reps)))
+        tu = float(np.median(T.time(lambda: lm.llama_unpack(c, back), reps)))
+        out[f"float_e{E}m{M}"] = {"pack_gbs": alg / tp / 1e6, "unpack_gbs": alg / tu / 1e6,
+                                  "pack_ms": tp, "unpack_ms": tu, "alg_bytes": alg}
+        c.close()
+    log("cfg3: int pack/unpack B=3..31")
+    g = torch.Generator(device="cuda").manual_seed(0)
+    u = torch.randint(0, 2 ** 31, (n_vals,), generator=g, device="cuda", dtype=torch.int64).to(torch.int32)
+    ints = {}
+    for B in range(3, 32):
+        # uniform over [-2^(B-1), 2^(B-1)): top B bits of a uniform 31-bit draw, recentred
+        vals = (u >> (31 - B)) - (1 << (B - 1))
+        s = lm.View(["i32"], {"kind": "soa_mb"}, [n_vals], blobs=[vals.view(torch.uint8)], index_type="u32")
+        c = lm.View(["i32"], {"kind": "bitpack_int", "bits": B}, [n_vals], index_type="u32")
+        lm.llama_pack(s, c)
+        lm.llama_unpack(c, back)
+        torch.cuda.synchronize()
+        if not torch.equal(back.blobs[0][: 4 * n_vals], s.blobs[0][: 4 * n_vals]):
+            raise SystemExit("int B=%d round trip is not exact" % B)
+        alg = 4 * n_vals + (n_vals * B + 7) // 8
+        tp = float(np.median(T.time(lambda: lm.llama_pack(s, c), reps)))
+        tu = float(np.median(T.time(lambda: lm.llama_unpack(c, back), reps)))
+        ints[B] = (alg / tp / 1e6, alg / tu / 1e6)
+        s.close()
+        c.close()
+        del vals
+    out["int"] = {"pack_gbs": {B: round(v[0], 1) for B, v in ints.items()},
+                  "unpack_gbs": {B: round(v[1], 1) for B, v in ints.items()},
+                  "pack_min_gbs": min(v[0] for v in ints.values()),
+                  "unpack_min_gbs": min(v[1] for v in ints.values())}
+    del u, bits
+    src.close()
+    back.close()
+    torch.cuda.empty_cache()
+    log("cfg3: ChangeType f64->f32 on %d records" % n_rec)
+    planes = synth.changetype_values(n_rec, 0)
+    mb = lm.View(["f64"] * 7, {"kind": "soa_mb"}, [n_rec], index_type="u32",
+                 blobs=[torch.from_numpy(p.view(np.uint8)).cuda() for p in planes])
+    del planes
+    aos = lm.View(["f64"] * 7, {"kind": "aos"}, [n_rec], index_type="u32")
+    lm.llama_copy(mb, aos)
+    ct = lm.View(["f64"] * 7, {"kind": "changetype", "stored": ["f32"] * 7, "inner": {"kind": "soa_mb"}},
+                 [n_rec], index_type="u32")
+    aos2 = lm.View(["f64"] * 7, {"kind": "aos"}, [n_rec], index_type="u32")
+    lm.llama_pack(aos, ct)
+    lm.llama_unpack(ct, aos2)
+    alg = n_rec * 56 + n_rec * 28
+    tp = float(np.median(T.time(lambda: lm.llama_pack(aos, ct), reps)))
+    tu = float(np.median(T.time(lambda: lm.llama_unpack(ct, aos2), reps)))
+    out["changetype_f64_f32"] = {"pack_gbs": alg / tp / 1e6, "unpack_gbs": alg / tu / 1e6,
+                                 "pack_ms": tp, "unpack_ms": tu, "alg_bytes": alg, "records": n_rec}
+    for v in (mb, aos, ct, aos2):
+        v.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+# ------------------------------------------------------------------ cfg4: batched
+
+def bench_cfg4(lm, torch, reps, count):
+    from paper_2302_08251_amd import synth
+    T = Timer(torch)
+    ns, pairs = synth.batch_views(count, 0)
+    log("cfg4: %d views, %d records" % (count, int(ns.sum())))
+    g = torch.Generator(device="cuda").manual_seed(0)
+    srcs, dsts = [], []
+    for n, p in zip(ns.tolist(), pairs.tolist()):
+        a, b = OFFDIAG[p]
+        s = lm.View(F32x7, LAYOUTS[a], [n], index_type="i32")
+        for t in s.blobs:
+            t.copy_(torch.randint(0, 256, t.shape, generator=g, device="cuda", dtype=torch.uint8))
+        srcs.append(s)
+        dsts.append(lm.View(F32x7, LAYOUTS[b], [n], index_type="i32"))
+    t0 = time.perf_counter()
+    try:
+        batch = lm.Batch(srcs, dsts, tune_cache=os.path.join(ROOT, "profiles", "batch_tune_cache.json"))
+    except lm.LlamaError as e:
+        return {"skipped": str(e)}
+    create_s = time.perf_counter() - t0
+    info = batch.info()
+    batch.launch()
+    batch.launch_per_view()
+    tb = T.time(batch.launch, reps)
+    tv = T.time(batch.launch_per_view, reps)
+    alg = info["algorithmic_bytes"]
+    res = {"views": count, "records": int(ns.sum()), "alg_bytes": alg,
+           "batched_ms": float(np.median(tb)), "per_view_ms": float(np.median(tv)),
+           "batched_gbs": alg / np.median(tb) / 1e6, "per_view_gbs": alg / np.median(tv) / 1e6,
+           "speedup": float(np.median(tv) / np.median(tb)), "tile_records": info["tile_records"],
+           "grid": info["grid"], "tune_seconds": info["tune_seconds"], "create_seconds": create_s}
+    batch.close()
+    for v in srcs + dsts:
+        v.close()
+    torch.cuda.empty_cache()
+    return res
+
+
+# ------------------------------------------------------------------ cfg5: n-body
+
+def bench_cfg5(lm, torch, n, steps):
+    from paper_2302_08251_amd import synth
+    T = Timer(torch)
+    out = {}
+    planes = synth.particles(n, 0, dtype=np.float64)
+    forms = {
+        "ChangeType(f64->f32, AoSoA-32)": {"kind": "changetype", "stored": ["f32"] * 7,
+                                           "inner": {"kind": "aosoa", "lanes": 32}},
+        "BitPackedFloat e8m15": {"kind": "bitpack_float", "exp": 8, "man": 15},
+    }
+    for name, spec in forms.items():
+        mb = lm.View(["f64"] * 7, {"kind": "soa_mb"}, [n],
+                     blobs=[torch.from_numpy(p.view(np.uint8).copy()).cuda() for p in planes])
+        v = lm.View(["f64"] * 7, spec, [n])
+        lm.llama_pack(mb, v)
+        e0 = lm.nbody_energy(v, 0.01)
+        lm.nbody_step(v, 1, 1e-4, 0.01)
+        ts = T.time(lambda: lm.nbody_step(v, 1, 1e-4, 0.01), steps)
+        e1 = lm.nbody_energy(v, 0.01)
+        te = T.time(lambda: lm.nbody_energy(v, 0.01), 2)
+        ms = float(np.median(ts))
+        inter = float(n) * n
+        out[name] = {"ms_per_step": ms, "interactions_per_s": inter / (ms * 1e-3),
+                     "gflops_20_per_interaction": 20 * inter / (ms * 1e-3) / 1e9,
+                     "frac_fp32_peak": 20 * inter / (ms * 1e-3) / (FP32_PEAK_TFLOPS * 1e12),
+                     "energy_ms": float(np.median(te)),
+                     "energy_drift_over_%d_steps" % (steps + 1): (e1 - e0) / abs(e0)}
+        mb.close()
+        v.close()
+    return out
+
+
+# ------------------------------------------------------------------ CPU oracle baseline
+
+def cpu_baseline(n_sample):
+    import oracle
+    from paper_2302_08251_amd import synth
+    threads = len(os.sched_getaffinity(0))
+    planes = synth.particles(n_sample, 0, dtype=np.float32)
+    tot_bytes, tot_s = 0, 0.0
+    sample_pairs = [("AoS", "SoA-MB"), ("SoA-SB", "AoSoA-32"), ("AoSoA-64", "Bytesplit")]
+    for a, b in sample_pairs:
+        src = oracle.store_planes(F32x7, LAYOUTS[a], planes, threads=threads)
+        dst = oracle.alloc_blobs(F32x7, LAYOUTS[b], n_sample)
+        t0 = time.perf_counter()
+        oracle.copy(F32x7, LAYOUTS[a], src, LAYOUTS[b], n_sample, dst_blobs=dst, threads=threads)
+        tot_s += time.perf_counter() - t0
+        tot_bytes += 2 * n_sample * 28
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": tot_bytes / tot_s / 1e9, "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": "%d records x 3 pairs (%s) of the 7xf32 workload, element-by-element oracle copy; cpu: %s" % (
+                n_sample, ", ".join("%s->%s" % p for p in sample_pairs), model),
+            "seconds": tot_s}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--records", type=int, default=64 << 20)
+    ap.add_argument("--rows", default="cfg3,cfg4,cfg5", help="extra rows to measure (comma list or 'none')")
+    ap.add_argument("--cpu-sample", type=int, default=2_000_000)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2302_08251_amd as lm
+    lm.lib()
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    torch.cuda.init()
+    rows = [] if args.rows == "none" else args.rows.split(",")
+    r2 = bench_cfg2(lm, torch, args.steps, args.warmup, args.records)
+    extra = {}
+    if "cfg3" in rows:
+        extra["cfg3"] = bench_cfg3(lm, torch, max(3, args.steps), 256 << 20, 64 << 20)
+    if "cfg4" in rows:
+        extra["cfg4"] = bench_cfg4(lm, torch, max(3, args.steps), 2000)
+    if "cfg5" in rows:
+        extra["cfg5"] = bench_cfg5(lm, torch, 65536, max(3, args.steps))
+    alg = r2["alg_bytes_per_pair"]
+    achieved = r2["gbs_step"]
+    traffic = measured_traffic(alg)
+    line = {
+        "metric": METRIC,
+        "value": round(r2["gbs_step"], 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r2["step_ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded numpy: pos U[-1,1], vel N(0,0.1), mass U[0.5,1])",
+        "config": {"workload": "single view: 64Mi records of 7 x f32, all 36 ordered pairs of "
+                               "AoS/SoA-SB/SoA-MB/AoSoA-32/AoSoA-64/Bytesplit(SoA-SB), I32 index",
+                   "records": r2["records"], "pairs": 36, "alg_bytes_per_step": 36 * alg},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
+        "cfg2": r2,
+    }
+    line.update(extra)
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,15 +1,345 @@
-// Batched copy (placeholder until the persistent batch kernel lands).
+// Batched copy: many views of uneven sizes and mixed mapping pairs moved by
+// one persistent kernel, captured once into a hipGraph and replayed.  The
+// tile size and the persistent grid are chosen by an autotuner that times
+// candidates on the batch itself; results are cached in a JSON file keyed by
+// device and batch shape.  The per-view baseline launches each view's own
+// copy back to back with its own tuned tile size.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <fstream>
+#include <sstream>
+
+#include "batch.hpp"
 #include "host.hpp"
 
 using namespace lm;
 
+struct llama_batch {
+  std::vector<const llama_view*> srcs;
+  std::vector<llama_view*> dsts;
+  uint32_t tile = 0, grid = 0, lds = 0, pv_tile = 0;
+  uint64_t total_tiles = 0, alg_bytes = 0;
+  double tune_seconds = 0;
+  BatchItem* d_items = nullptr;
+  uint32_t* d_prefix = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<Plan> pv;
+};
+
+namespace {
+
+llama_status hip_fail(hipError_t e, const char* what) {
+  return fail(LLAMA_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void release_device(llama_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_prefix) (void)hipFree(b->d_prefix);
+  b->d_items = nullptr;
+  b->d_prefix = nullptr;
+}
+
+// Work list for tile size T: per-view plans, tile prefix sums, max LDS.
+llama_status build_items(llama_batch* b, uint32_t T, std::vector<BatchItem>& items, std::vector<uint32_t>& prefix,
+                         uint32_t& lds) {
+  const size_t n = b->srcs.size();
+  items.assign(n, BatchItem{});
+  prefix.assign(n + 1, 0);
+  lds = 0;
+  uint64_t total = 0;
+  for (size_t v = 0; v < n; ++v) {
+    Plan p;
+    llama_launch_params lp{T, 0};
+    llama_status st = plan_copy(b->srcs[v], b->dsts[v], &lp, p);
+    if (st != LLAMA_OK) return st;
+    if (p.kind != PK_RAW) return fail(LLAMA_ERR_UNSUPPORTED, "batched copies move physical layouts only");
+    items[v].args = p.args;
+    items[v].unit = p.unit;
+    total += p.ntiles;
+    if (total >= 0x80000000ull) return fail(LLAMA_ERR_INDEX_OVERFLOW, "batch has too many tiles");
+    prefix[v + 1] = (uint32_t)total;
+    lds = std::max(lds, p.lds);
+  }
+  return LLAMA_OK;
+}
+
+llama_status upload(llama_batch* b, uint32_t T) {
+  std::vector<BatchItem> items;
+  std::vector<uint32_t> prefix;
+  uint32_t lds;
+  llama_status st = build_items(b, T, items, prefix, lds);
+  if (st != LLAMA_OK) return st;
+  release_device(b);
+  hipError_t e;
+  if ((e = hipMalloc(&b->d_items, items.size() * sizeof(BatchItem))) != hipSuccess) return hip_fail(e, "hipMalloc");
+  if ((e = hipMalloc(&b->d_prefix, prefix.size() * sizeof(uint32_t))) != hipSuccess) return hip_fail(e, "hipMalloc");
+  if ((e = hipMemcpy(b->d_items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e, "hipMemcpy");
+  if ((e = hipMemcpy(b->d_prefix, prefix.data(), prefix.size() * sizeof(uint32_t), hipMemcpyHostToDevice)) !=
+      hipSuccess)
+    return hip_fail(e, "hipMemcpy");
+  b->tile = T;
+  b->lds = lds;
+  b->total_tiles = prefix.back();
+  return LLAMA_OK;
+}
+
+llama_status capture(llama_batch* b) {
+  hipError_t e;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+    return hip_fail(e, "hipStreamBeginCapture");
+  hipError_t le = launch_batch(b->d_items, b->d_prefix, (uint32_t)b->total_tiles, b->grid, b->lds, b->cap);
+  e = hipStreamEndCapture(b->cap, &b->graph);
+  if (le != hipSuccess) return hip_fail(le, "batched launch");
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess)
+    return hip_fail(e, "hipGraphInstantiate");
+  return LLAMA_OK;
+}
+
+llama_status per_view_plans(llama_batch* b, uint32_t T, std::vector<Plan>& out) {
+  out.resize(b->srcs.size());
+  for (size_t v = 0; v < b->srcs.size(); ++v) {
+    llama_launch_params lp{T, 0};
+    llama_status st = plan_copy(b->srcs[v], b->dsts[v], &lp, out[v]);
+    if (st != LLAMA_OK) return st;
+  }
+  return LLAMA_OK;
+}
+
+// median of `reps` timings (ms) of fn on stream s
+template <typename F>
+double time_ms(hipStream_t s, int reps, F&& fn) {
+  hipEvent_t a, c;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&c);
+  std::vector<double> t;
+  for (int r = 0; r < reps; ++r) {
+    (void)hipEventRecord(a, s);
+    fn();
+    (void)hipEventRecord(c, s);
+    (void)hipEventSynchronize(c);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, a, c);
+    t.push_back(ms);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(c);
+  std::sort(t.begin(), t.end());
+  return t[t.size() / 2];
+}
+
+std::string device_key(const llama_batch* b) {
+  int dev = 0, cus = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  hipDeviceProp_t prop;
+  std::string arch = "gpu";
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+  for (auto& ch : arch)
+    if (ch == '"' || ch == '\\') ch = '_';
+  uint64_t recs = 0, h = 1469598103934665603ull;
+  for (size_t v = 0; v < b->srcs.size(); ++v) {
+    recs += b->srcs[v]->n;
+    uint64_t x = (uint64_t)b->srcs[v]->map.kind * 131 + b->dsts[v]->map.kind * 7 + b->srcs[v]->map.lanes * 1009 +
+                 b->dsts[v]->map.lanes * 9176 + (b->srcs[v]->map.inner ? 3 : 0) + (b->dsts[v]->map.inner ? 5 : 0) +
+                 b->srcs[v]->n * 31 + b->srcs[v]->rec.size();
+    h = (h ^ x) * 1099511628211ull;
+  }
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s|cu%d|views%zu|records%llu|shape%016llx", arch.c_str(), cus, b->srcs.size(),
+                (unsigned long long)recs, (unsigned long long)h);
+  return buf;
+}
+
+bool cache_lookup(const char* path, const std::string& key, uint32_t& T, uint32_t& G, uint32_t& P) {
+  std::ifstream f(path);
+  if (!f) return false;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string s = ss.str();
+  const size_t k = s.find("\"" + key + "\"");
+  if (k == std::string::npos) return false;
+  auto num = [&](const char* name, uint32_t& out) {
+    size_t p = s.find(std::string("\"") + name + "\"", k);
+    if (p == std::string::npos) return false;
+    p = s.find(':', p);
+    if (p == std::string::npos) return false;
+    out = (uint32_t)std::strtoul(s.c_str() + p + 1, nullptr, 10);
+    return out > 0;
+  };
+  return num("tile_records", T) && num("grid", G) && num("per_view_tile", P);
+}
+
+void cache_store(const char* path, const std::string& key, uint32_t T, uint32_t G, uint32_t P) {
+  // keep the other entries: the file holds one entry per line
+  std::vector<std::string> lines;
+  {
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line))
+      if (line.rfind("  \"", 0) == 0 && line.find("\"" + key + "\"") == std::string::npos) {
+        if (!line.empty() && line.back() == ',') line.pop_back();
+        lines.push_back(line);
+      }
+  }
+  char buf[512];
+  std::snprintf(buf, sizeof(buf), "  \"%s\": {\"tile_records\": %u, \"grid\": %u, \"per_view_tile\": %u}",
+                key.c_str(), T, G, P);
+  lines.push_back(buf);
+  std::ofstream o(path, std::ios::trunc);
+  if (!o) return;
+  o << "{\n";
+  for (size_t i = 0; i < lines.size(); ++i) o << lines[i] << (i + 1 < lines.size() ? ",\n" : "\n");
+  o << "}\n";
+}
+
+llama_status autotune(llama_batch* b, uint64_t granule, uint32_t& bestT, uint32_t& bestG, uint32_t& bestP) {
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  std::vector<uint32_t> tiles;
+  for (uint32_t T : {256u, 512u, 1024u, 2048u})
+    if (T % granule == 0) tiles.push_back(T);
+  if (tiles.empty()) tiles.push_back((uint32_t)granule);
+  double best = 1e30, best_pv = 1e30;
+  bestT = bestG = bestP = 0;
+  for (uint32_t T : tiles) {
+    if (upload(b, T) != LLAMA_OK) continue;  // e.g. a tile that does not fit in LDS
+    for (uint32_t mult : {4u, 8u, 16u, 32u}) {
+      const uint32_t G = (uint32_t)std::min<uint64_t>((uint64_t)cus * mult, b->total_tiles);
+      hipError_t le = hipSuccess;
+      auto run = [&]() {
+        hipError_t e = launch_batch(b->d_items, b->d_prefix, (uint32_t)b->total_tiles, G, b->lds, b->cap);
+        if (e != hipSuccess) le = e;
+      };
+      run();
+      const double ms = time_ms(b->cap, 3, run);
+      if (le != hipSuccess) return hip_fail(le, "batched launch");
+      if (ms < best) {
+        best = ms;
+        bestT = T;
+        bestG = G;
+      }
+    }
+    std::vector<Plan> pv;
+    if (per_view_plans(b, T, pv) != LLAMA_OK) continue;
+    auto run_pv = [&]() {
+      for (auto& p : pv) (void)launch_plan(p, b->cap);
+    };
+    run_pv();
+    const double ms = time_ms(b->cap, 2, run_pv);
+    if (ms < best_pv) {
+      best_pv = ms;
+      bestP = T;
+    }
+  }
+  if (!bestT || !bestP) return fail(LLAMA_ERR_UNSUPPORTED, "no tile size fits every view of the batch");
+  return LLAMA_OK;
+}
+
+}  // namespace
+
 extern "C" {
-llama_status llama_batch_create(uint32_t, const llama_view* const*, llama_view* const*, const char*, llama_batch** out) {
-  if (out) *out = nullptr;
-  return fail(LLAMA_ERR_UNSUPPORTED, "batched copy not built yet");
+
+llama_status llama_batch_create(uint32_t n, const llama_view* const* srcs, llama_view* const* dsts,
+                                const char* tune_cache, llama_batch** out) {
+  clear_error();
+  if (!out) return fail(LLAMA_ERR_INVALID_ARG, "output pointer is NULL");
+  *out = nullptr;
+  if (n == 0 || !srcs || !dsts) return fail(LLAMA_ERR_INVALID_ARG, "empty batch");
+  std::unique_ptr<llama_batch> b(new llama_batch);
+  uint64_t granule = 128;
+  for (uint32_t v = 0; v < n; ++v) {
+    if (!srcs[v] || !dsts[v]) return fail(LLAMA_ERR_INVALID_ARG, "view is NULL");
+    Plan p;
+    llama_status st = plan_copy(srcs[v], dsts[v], nullptr, p);
+    if (st != LLAMA_OK) return fail(st, "view " + std::to_string(v) + ": " + llama_last_error());
+    if (p.kind != PK_RAW) return fail(LLAMA_ERR_UNSUPPORTED, "batched copies move physical layouts only");
+    granule = std::max<uint64_t>(granule, tile_granule(p.args.src, p.args.dst));
+    if (granule % tile_granule(p.args.src, p.args.dst)) return fail(LLAMA_ERR_UNSUPPORTED, "incompatible AoSoA lanes");
+    b->srcs.push_back(srcs[v]);
+    b->dsts.push_back(dsts[v]);
+    b->alg_bytes += p.alg_bytes;
+  }
+  hipError_t e = hipStreamCreate(&b->cap);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+  const std::string key = device_key(b.get());
+  uint32_t T = 0, G = 0, P = 0;
+  llama_status st;
+  if (!(tune_cache && cache_lookup(tune_cache, key, T, G, P))) {
+    const auto t0 = std::chrono::steady_clock::now();
+    if ((st = autotune(b.get(), granule, T, G, P)) != LLAMA_OK) {
+      release_device(b.get());
+      (void)hipStreamDestroy(b->cap);
+      return st;
+    }
+    b->tune_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (tune_cache) cache_store(tune_cache, key, T, G, P);
+  }
+  b->grid = G;
+  b->pv_tile = P;
+  if ((st = upload(b.get(), T)) != LLAMA_OK || (st = per_view_plans(b.get(), P, b->pv)) != LLAMA_OK ||
+      (st = capture(b.get())) != LLAMA_OK) {
+    release_device(b.get());
+    (void)hipStreamDestroy(b->cap);
+    return st;
+  }
+  *out = b.release();
+  return LLAMA_OK;
 }
-llama_status llama_batch_launch(llama_batch*, void*) { return fail(LLAMA_ERR_UNSUPPORTED, "batched copy not built yet"); }
-llama_status llama_batch_launch_per_view(llama_batch*, void*) { return fail(LLAMA_ERR_UNSUPPORTED, "batched copy not built yet"); }
-llama_status llama_batch_get_info(const llama_batch*, llama_batch_info*) { return fail(LLAMA_ERR_UNSUPPORTED, "batched copy not built yet"); }
-llama_status llama_batch_destroy(llama_batch*) { return LLAMA_OK; }
+
+llama_status llama_batch_launch(llama_batch* b, void* stream) {
+  clear_error();
+  if (!b || !b->exec) return fail(LLAMA_ERR_INVALID_ARG, "batch is NULL");
+  hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return LLAMA_OK;
 }
+
+llama_status llama_batch_launch_per_view(llama_batch* b, void* stream) {
+  clear_error();
+  if (!b) return fail(LLAMA_ERR_INVALID_ARG, "batch is NULL");
+  for (auto& p : b->pv) {
+    llama_status st = launch_plan(p, (hipStream_t)stream);
+    if (st != LLAMA_OK) return st;
+  }
+  return LLAMA_OK;
+}
+
+llama_status llama_batch_get_info(const llama_batch* b, llama_batch_info* info) {
+  clear_error();
+  if (!b || !info) return fail(LLAMA_ERR_INVALID_ARG, "NULL argument");
+  info->n_views = (uint32_t)b->srcs.size();
+  info->tile_records = b->tile;
+  info->grid = b->grid;
+  info->total_tiles = b->total_tiles;
+  info->algorithmic_bytes = b->alg_bytes;
+  info->tune_seconds = b->tune_seconds;
+  return LLAMA_OK;
+}
+
+llama_status llama_batch_destroy(llama_batch* b) {
+  clear_error();
+  if (!b) return LLAMA_OK;
+  if (b->cap) (void)hipStreamSynchronize(b->cap);
+  release_device(b);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  delete b;
+  return LLAMA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,18 @@
+// Work items of the persistent batched copy.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace lm {
+
+struct BatchItem {
+  TileArgs args;   // the view's single-launch plan (tile size shared by the batch)
+  uint32_t unit;   // raw-copy unit in bytes (1, 2, 4, 8)
+  uint32_t pad[3];
+};
+
+hipError_t launch_batch(const BatchItem* items, const uint32_t* prefix, uint32_t total_tiles, uint32_t grid,
+                        uint32_t lds, hipStream_t st);
+
+}  // namespace lm

@@ -1,0 +1,41 @@
+// Persistent batched copy: one launch moves the tiles of many views with
+// mixed mapping pairs.  The global tile index space is the concatenation of
+// every view's tiles (prefix sums in `prefix`); workgroup b takes tiles
+// b, b + G, b + 2G, ... so consecutive tiles of one view spread over all
+// XCDs and every workgroup gets the same number of tiles.  The per-tile work
+// is the single-view tile engine, selected by the view's unit size with a
+// wave-uniform branch.
+#include "batch.hpp"
+#include "kernels.hpp"
+
+namespace lm {
+
+__global__ __launch_bounds__(kThreads) void k_batch(const BatchItem* __restrict__ items,
+                                                   const uint32_t* __restrict__ prefix, uint32_t total_tiles) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+  uint32_t v = 0;
+  for (uint32_t t = blockIdx.x; t < total_tiles; t += gridDim.x) {
+    while (prefix[v + 1] <= t) ++v;  // tiles are visited in increasing order
+    const BatchItem& it = items[v];
+    const uint64_t i0 = (uint64_t)(t - prefix[v]) * it.args.tile;
+    const uint64_t left = it.args.src.n - i0;
+    const uint32_t nt = left < (uint64_t)it.args.tile ? (uint32_t)left : it.args.tile;
+    load_tile(it.args.src, i0, nt, lds);
+    wait_tile_loads();
+    switch (it.unit) {
+      case 1: phase_b_raw<1>(it.args.src, it.args.dst, i0, nt, lds); break;
+      case 2: phase_b_raw<2>(it.args.src, it.args.dst, i0, nt, lds); break;
+      case 4: phase_b_raw<4>(it.args.src, it.args.dst, i0, nt, lds); break;
+      default: phase_b_raw<8>(it.args.src, it.args.dst, i0, nt, lds); break;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_batch(const BatchItem* items, const uint32_t* prefix, uint32_t total_tiles, uint32_t grid,
+                        uint32_t lds, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kThreads), lds, st, items, prefix, total_tiles);
+  return hipGetLastError();
+}
+
+}  // namespace lm

@@ -1,0 +1,78 @@
+"""Batched copy: many views of uneven sizes with mixed mapping pairs moved by
+one persistent, hipGraph-captured launch; every destination must equal the
+oracle's copy, on every graph replay, and equal the per-view launches."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import CFG2, F32x7, assert_blobs_equal, bits_planes, download, gpu_view, say
+
+import paper_2302_08251_amd as lm
+from paper_2302_08251_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+NAMES = list(CFG2)
+OFFDIAG = [(a, b) for a in NAMES for b in NAMES if a != b]
+
+
+def make_batch(count, lo, hi, seed):
+    ns, pairs = synth.batch_views(count, seed, lo, hi)
+    views = []
+    for k, (n, p) in enumerate(zip(ns.tolist(), pairs.tolist())):
+        a, b = OFFDIAG[p]
+        planes = bits_planes(n, F32x7, seed=seed * 1000 + k)
+        src_host = oracle.store_planes(F32x7, CFG2[a], planes, fill=0x5A)
+        exp = oracle.copy(F32x7, CFG2[a], src_host, CFG2[b], n, fill=0xA5)
+        views.append((gpu_view(F32x7, CFG2[a], n, src_host), gpu_view(F32x7, CFG2[b], n, fill=0xA5), exp, (a, b, n)))
+    return views
+
+
+def check(views, what):
+    for sv, dv, exp, tag in views:
+        assert_blobs_equal(download(dv), exp, "%s %s" % (what, tag))
+
+
+def reset(views):
+    for _, dv, _, _ in views:
+        for t in dv.blobs:
+            t.fill_(0xA5)
+
+
+def test_batch_graph_replays_match_oracle():
+    torch = pytest.importorskip("torch")
+    views = make_batch(120, 1, 30000, seed=1)
+    batch = lm.Batch([v[0] for v in views], [v[1] for v in views])
+    info = batch.info()
+    say("batch info", info)
+    assert info["n_views"] == 120 and info["tile_records"] % 128 == 0
+    reset(views)
+    for rep in range(3):
+        batch.launch()
+        torch.cuda.synchronize()
+        check(views, "graph replay %d" % rep)
+        reset(views)  # eager work between replays
+        x = torch.ones(1 << 20, device="cuda").sum()
+        assert float(x) == float(1 << 20)
+        torch.cuda.synchronize()
+    batch.launch_per_view()
+    check(views, "per-view")
+    batch.close()
+
+
+def test_batch_tune_cache_roundtrip(tmp_path):
+    torch = pytest.importorskip("torch")
+    views = make_batch(40, 100, 5000, seed=2)
+    path = str(tmp_path / "tune.json")
+    b1 = lm.Batch([v[0] for v in views], [v[1] for v in views], tune_cache=path)
+    i1 = b1.info()
+    assert i1["tune_seconds"] > 0
+    b2 = lm.Batch([v[0] for v in views], [v[1] for v in views], tune_cache=path)
+    i2 = b2.info()
+    assert i2["tune_seconds"] == 0 and (i2["tile_records"], i2["grid"]) == (i1["tile_records"], i1["grid"])
+    reset(views)
+    b2.launch()
+    torch.cuda.synchronize()
+    check(views, "cached batch")
+    b1.close()
+    b2.close()
