@@ -18,6 +18,7 @@ import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -182,19 +183,20 @@ def bench_cfg3(lm, torch, reps, n_vals, n_rec):
     g = torch.Generator(device="cuda").manual_seed(0)
     u = torch.randint(0, 2 ** 31, (n_vals,), generator=g, device="cuda", dtype=torch.int64).to(torch.int32)
     ints = {}
+    iback = lm.View(["i32"], {"kind": "soa_mb"}, [n_vals], index_type="u32")
     for B in range(3, 32):
         # uniform over [-2^(B-1), 2^(B-1)): top B bits of a uniform 31-bit draw, recentred
         vals = (u >> (31 - B)) - (1 << (B - 1))
         s = lm.View(["i32"], {"kind": "soa_mb"}, [n_vals], blobs=[vals.view(torch.uint8)], index_type="u32")
         c = lm.View(["i32"], {"kind": "bitpack_int", "bits": B}, [n_vals], index_type="u32")
         lm.llama_pack(s, c)
-        lm.llama_unpack(c, back)
+        lm.llama_unpack(c, iback)
         torch.cuda.synchronize()
-        if not torch.equal(back.blobs[0][: 4 * n_vals], s.blobs[0][: 4 * n_vals]):
+        if not torch.equal(iback.blobs[0][: 4 * n_vals], s.blobs[0][: 4 * n_vals]):
             raise SystemExit("int B=%d round trip is not exact" % B)
         alg = 4 * n_vals + (n_vals * B + 7) // 8
         tp = float(np.median(T.time(lambda: lm.llama_pack(s, c), reps)))
-        tu = float(np.median(T.time(lambda: lm.llama_unpack(c, back), reps)))
+        tu = float(np.median(T.time(lambda: lm.llama_unpack(c, iback), reps)))
         ints[B] = (alg / tp / 1e6, alg / tu / 1e6)
         s.close()
         c.close()
@@ -206,6 +208,7 @@ def bench_cfg3(lm, torch, reps, n_vals, n_rec):
     del u, bits
     src.close()
     back.close()
+    iback.close()
     torch.cuda.empty_cache()
     log("cfg3: ChangeType f64->f32 on %d records" % n_rec)
     planes = synth.changetype_values(n_rec, 0)
@@ -248,7 +251,9 @@ def bench_cfg4(lm, torch, reps, count):
         dsts.append(lm.View(F32x7, LAYOUTS[b], [n], index_type="i32"))
     t0 = time.perf_counter()
     try:
-        batch = lm.Batch(srcs, dsts, tune_cache=os.path.join(ROOT, "profiles", "batch_tune_cache.json"))
+        cache = os.environ.get("LLAMA_MI_TUNE_CACHE",
+                               os.path.join(tempfile.gettempdir(), "llama_mi_batch_tune.json"))
+        batch = lm.Batch(srcs, dsts, tune_cache=cache)
     except lm.LlamaError as e:
         return {"skipped": str(e)}
     create_s = time.perf_counter() - t0
@@ -357,12 +362,17 @@ def main():
     rows = [] if args.rows == "none" else args.rows.split(",")
     r2 = bench_cfg2(lm, torch, args.steps, args.warmup, args.records)
     extra = {}
-    if "cfg3" in rows:
-        extra["cfg3"] = bench_cfg3(lm, torch, max(3, args.steps), 256 << 20, 64 << 20)
-    if "cfg4" in rows:
-        extra["cfg4"] = bench_cfg4(lm, torch, max(3, args.steps), 2000)
-    if "cfg5" in rows:
-        extra["cfg5"] = bench_cfg5(lm, torch, 65536, max(3, args.steps))
+    row_fns = {"cfg3": lambda: bench_cfg3(lm, torch, max(3, args.steps), 256 << 20, 64 << 20),
+               "cfg4": lambda: bench_cfg4(lm, torch, max(3, args.steps), 2000),
+               "cfg5": lambda: bench_cfg5(lm, torch, 65536, max(3, args.steps))}
+    for r in rows:
+        try:
+            extra[r] = row_fns[r]()
+        except (lm.LlamaError, SystemExit) as e:  # a failing row is reported, not hidden
+            extra[r] = {"error": str(e)}
+            log("row %s failed: %s" % (r, e))
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
     alg = r2["alg_bytes_per_pair"]
     achieved = r2["gbs_step"]
     traffic = measured_traffic(alg)

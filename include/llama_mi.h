@@ -194,7 +194,8 @@ llama_status llama_copy_ex(const llama_view* src, llama_view* dst,
  * parameters: read when it holds an entry for this device and batch shape,
  * otherwise the autotuner times candidates on the batch itself (this
  * overwrites destination blobs) and writes the entry.  NULL = always tune,
- * write nothing.  The launch is captured into a hipGraph on first use. */
+ * write nothing.  Creation synchronizes the device first.  The launch is
+ * captured into a hipGraph at creation. */
 llama_status llama_batch_create(uint32_t n, const llama_view* const* srcs,
                                 llama_view* const* dsts, const char* tune_cache,
                                 llama_batch** out);

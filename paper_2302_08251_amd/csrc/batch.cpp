@@ -275,7 +275,11 @@ llama_status llama_batch_create(uint32_t n, const llama_view* const* srcs, llama
     b->dsts.push_back(dsts[v]);
     b->alg_bytes += p.alg_bytes;
   }
-  hipError_t e = hipStreamCreate(&b->cap);
+  // the autotuner runs copies on a private stream: earlier work on any stream
+  // (for example the writes that fill the sources) must be complete
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  e = hipStreamCreate(&b->cap);
   if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
   const std::string key = device_key(b.get());
   uint32_t T = 0, G = 0, P = 0;
@@ -292,6 +296,7 @@ llama_status llama_batch_create(uint32_t n, const llama_view* const* srcs, llama
   }
   b->grid = G;
   b->pv_tile = P;
+  (void)hipStreamSynchronize(b->cap);
   if ((st = upload(b.get(), T)) != LLAMA_OK || (st = per_view_plans(b.get(), P, b->pv)) != LLAMA_OK ||
       (st = capture(b.get())) != LLAMA_OK) {
     release_device(b.get());

@@ -2,6 +2,7 @@
 // and dispatch of the tile kernels.
 #include "host.hpp"
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstring>
 
@@ -422,12 +423,16 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     else return fail(LLAMA_ERR_UNSUPPORTED, "the GPU path converts between F64 and F32 only");
   }
   const uint64_t gran = tile_granule(S, D);
+  // bytes of one destination tile segment set: the destination inverse
+  // divides offsets below tile * S by up to L * S, exact while that product
+  // stays below 2^32, i.e. tile * S <= 65536
+  const uint64_t dst_bytes = D.layout == LY_STREAM ? 0 : (uint64_t)D.rec_bytes;
   uint64_t tile = p && p->tile_records ? p->tile_records : 0;
   if (tile) {
     if (tile % gran) return fail(LLAMA_ERR_INVALID_ARG, "tile_records must be a multiple of " + std::to_string(gran));
   } else {
-    // about 16 KiB of LDS per tile
-    const uint64_t per = tile_lds_bytes(S, (uint32_t)gran);
+    // about 16 KiB per tile on the larger side
+    uint64_t per = std::max<uint64_t>(tile_lds_bytes(S, (uint32_t)gran), gran * dst_bytes);
     uint64_t k = per ? (16384 / per) : 1;
     if (k < 1) k = 1;
     tile = gran * k;
@@ -438,8 +443,9 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     return fail(tile == gran ? LLAMA_ERR_UNSUPPORTED : LLAMA_ERR_INVALID_ARG,
                 "a tile of " + std::to_string(tile) + " records needs " + std::to_string(lds) +
                     " bytes of LDS (limit 65536); reduce the tile or the AoSoA lane count");
-  if (tile * D.rec_bytes > kMaxTileLds * 2ull && D.layout != LY_STREAM)
-    return fail(LLAMA_ERR_INVALID_ARG, "destination tile too large");
+  if (tile * dst_bytes > 65536)
+    return fail(tile == gran ? LLAMA_ERR_UNSUPPORTED : LLAMA_ERR_INVALID_ARG,
+                "a destination tile of " + std::to_string(tile) + " records spans more than 65536 bytes");
   S.lds_stride = lds_stride(S, (uint32_t)tile);
   D.lds_stride = lds_stride(D, (uint32_t)tile);
   plan.args.tile = (uint32_t)tile;

@@ -17,6 +17,8 @@ from paper_2302_08251_amd import synth
 pytestmark = pytest.mark.gpu
 
 EPS2, DT = 0.01, 1e-4
+# the ABI takes eps2 as float32; the FP64 energy widens that value exactly
+EPS2_F = float(np.float32(EPS2))
 CT_AOSOA32 = {"kind": "changetype", "stored": ["f32"] * 7, "inner": {"kind": "aosoa", "lanes": 32}}
 E8M15 = {"kind": "bitpack_float", "exp": 8, "man": 15}
 
@@ -77,8 +79,8 @@ def test_cfg5_f32_form_full_size():
         say("cfg5 ChangeType(f64->f32, AoSoA-32) steps=%d pos %.3g vel %.3g" % (steps, ex, ev))
         assert ex <= 1e-5 and ev <= 1e-5
     e_gpu = lm.nbody_energy(view, EPS2)
-    e_ref = oracle.energy(gp, gv, m, EPS2)
-    e0 = oracle.energy(p0, v0, m, EPS2)
+    e_ref = oracle.energy(gp, gv, m, EPS2_F)
+    e0 = oracle.energy(p0, v0, m, EPS2_F)
     say("energy gpu %.12g oracle-of-gpu-state %.12g drift %.3g" % (e_gpu, e_ref, (e_gpu - e0) / abs(e0)))
     assert abs(e_gpu - e_ref) <= 1e-10 * abs(e_ref)
 
@@ -98,4 +100,4 @@ def test_energy_matches_oracle():
     p, v, m = state(oracle.load_planes(F64x7, CT_AOSOA32, host, n))
     view = gpu_view(F64x7, CT_AOSOA32, n, host)
     e = lm.nbody_energy(view, EPS2)
-    assert abs(e - oracle.energy(p, v, m, EPS2)) <= 1e-11 * abs(e)
+    assert abs(e - oracle.energy(p, v, m, EPS2_F)) <= 1e-11 * abs(e)
