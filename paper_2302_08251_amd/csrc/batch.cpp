@@ -14,6 +14,7 @@
 
 #include "batch.hpp"
 #include "host.hpp"
+#include "kernels.hpp"
 
 using namespace lm;
 
@@ -48,26 +49,43 @@ void release_device(llama_batch* b) {
   b->d_prefix = nullptr;
 }
 
-// Work list for tile size T: per-view plans, tile prefix sums, max LDS.
+// Work list for tile size T: per-view plans, tile prefix sums, max LDS.  The
+// views are ordered by copy variant (leaf bytes, relayout mode, layouts) so
+// that the persistent workgroups, which walk the tile space in order, keep
+// one variant's code hot at a time.
 llama_status build_items(llama_batch* b, uint32_t T, std::vector<BatchItem>& items, std::vector<uint32_t>& prefix,
                          uint32_t& lds) {
   const size_t n = b->srcs.size();
-  items.assign(n, BatchItem{});
-  prefix.assign(n + 1, 0);
+  std::vector<BatchItem> plans(n);
+  std::vector<uint64_t> tiles(n);
+  std::vector<uint64_t> key(n);
   lds = 0;
-  uint64_t total = 0;
   for (size_t v = 0; v < n; ++v) {
     Plan p;
     llama_launch_params lp{T, 0};
     llama_status st = plan_copy(b->srcs[v], b->dsts[v], &lp, p);
     if (st != LLAMA_OK) return st;
     if (p.kind != PK_RAW) return fail(LLAMA_ERR_UNSUPPORTED, "batched copies move physical layouts only");
-    items[v].args = p.args;
-    items[v].unit = p.unit;
-    total += p.ntiles;
-    if (total >= 0x80000000ull) return fail(LLAMA_ERR_INDEX_OVERFLOW, "batch has too many tiles");
-    prefix[v + 1] = (uint32_t)total;
+    plans[v] = BatchItem{};
+    plans[v].args = p.args;
+    plans[v].unit = p.unit;
+    plans[v].variant = raw_variant(p.args, p.unit);
+    tiles[v] = p.ntiles;
+    key[v] = ((uint64_t)p.unit << 40) | ((uint64_t)plans[v].variant << 32) | ((uint64_t)p.args.dst.layout << 24) |
+             ((uint64_t)p.args.src.layout << 16) | ((uint64_t)p.args.colrun << 8);
     lds = std::max(lds, p.lds);
+  }
+  std::vector<size_t> order(n);
+  for (size_t v = 0; v < n; ++v) order[v] = v;
+  std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return key[x] < key[y]; });
+  items.assign(n, BatchItem{});
+  prefix.assign(n + 1, 0);
+  uint64_t total = 0;
+  for (size_t k = 0; k < n; ++k) {
+    items[k] = plans[order[k]];
+    total += tiles[order[k]];
+    if (total >= 0x80000000ull) return fail(LLAMA_ERR_INDEX_OVERFLOW, "batch has too many tiles");
+    prefix[k + 1] = (uint32_t)total;
   }
   return LLAMA_OK;
 }

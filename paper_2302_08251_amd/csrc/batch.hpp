@@ -8,8 +8,9 @@ namespace lm {
 
 struct BatchItem {
   TileArgs args;   // the view's single-launch plan (tile size shared by the batch)
-  uint32_t unit;   // raw-copy unit in bytes (1, 2, 4, 8)
-  uint32_t pad[3];
+  uint32_t unit;     // leaf bytes of the record (1, 2, 4, 8)
+  uint32_t variant;  // raw-copy variant (RawVariant)
+  uint32_t pad[2];
 };
 
 hipError_t launch_batch(const BatchItem* items, const uint32_t* prefix, uint32_t total_tiles, uint32_t grid,

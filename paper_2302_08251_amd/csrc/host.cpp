@@ -250,8 +250,12 @@ static llama_status physical_side(const MapDesc& m, uint32_t nf, uint32_t es, Si
   uint32_t cs = es, ncols = nf;
   if (m.kind == LLAMA_MAP_BYTESPLIT) {
     p = m.inner.get();
-    cs = 1;
-    ncols = nf * es;
+    // Bytesplit over AoS places byte k of field f at i*S + p_f + k: the
+    // packed AoS byte image itself, so it is moved as an AoS of elements
+    if (p->kind != LLAMA_MAP_AOS) {
+      cs = 1;
+      ncols = nf * es;
+    }
   }
   s.cs = cs;
   s.log2cs = log2u(cs);
@@ -410,7 +414,8 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     plan.args.codec = codec_of(su);
   } else if (S.vkind == VK_RAW && D.vkind == VK_RAW) {
     plan.kind = PK_RAW;
-    plan.unit = S.cs < D.cs ? S.cs : D.cs;
+    plan.unit = S.es;  // leaf bytes
+    plan.args.mode = S.cs == D.cs ? RM_DIRECT : (S.cs == 1 ? RM_MERGE : RM_SPLIT);
   } else if (S.vkind == VK_CONV && D.vkind == VK_CONV) {
     return fail(LLAMA_ERR_UNSUPPORTED, "copy between two ChangeType views with conversions");
   } else {
@@ -422,6 +427,18 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     else if (from == LLAMA_F32 && to == LLAMA_F64) plan.args.conv = CV_F32_F64;
     else return fail(LLAMA_ERR_UNSUPPORTED, "the GPU path converts between F64 and F32 only");
   }
+  const uint32_t mode = plan.kind == PK_RAW ? plan.args.mode : RM_DIRECT;
+  // canonical planar image of a relayout: element planes (MERGE) or byte planes (SPLIT)
+  const uint32_t F = (uint32_t)src->rec.size(), ES = S.es;
+  auto can_bytes = [&](uint64_t t) -> uint64_t {
+    if (mode == RM_MERGE) return (uint64_t)F * (t * ES + 16u);
+    if (mode == RM_SPLIT) return (uint64_t)F * ES * (t + 16u);
+    return 0;
+  };
+  auto lds_total = [&](uint64_t t) -> uint64_t {
+    const uint64_t a = tile_lds_bytes(S, (uint32_t)t);
+    return mode == RM_DIRECT ? a : ((a + 15u) & ~15ull) + can_bytes(t);
+  };
   const uint64_t gran = tile_granule(S, D);
   // bytes of one destination tile segment set: the destination inverse
   // divides offsets below tile * S by up to L * S, exact while that product
@@ -431,14 +448,15 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
   if (tile) {
     if (tile % gran) return fail(LLAMA_ERR_INVALID_ARG, "tile_records must be a multiple of " + std::to_string(gran));
   } else {
-    // about 16 KiB per tile on the larger side
-    uint64_t per = std::max<uint64_t>(tile_lds_bytes(S, (uint32_t)gran), gran * dst_bytes);
-    uint64_t k = per ? (16384 / per) : 1;
+    // about 16 KiB per tile image on the larger side (32 KiB with a relayout)
+    const uint64_t target = mode == RM_DIRECT ? 16384 : 32768;
+    uint64_t per = std::max<uint64_t>(lds_total(gran), gran * dst_bytes);
+    uint64_t k = per ? (target / per) : 1;
     if (k < 1) k = 1;
     tile = gran * k;
   }
   if (tile > 65536) return fail(LLAMA_ERR_INVALID_ARG, "tile_records must be <= 65536");
-  const uint64_t lds = tile_lds_bytes(S, (uint32_t)tile);
+  const uint64_t lds = lds_total(tile);
   if (lds > kMaxTileLds)
     return fail(tile == gran ? LLAMA_ERR_UNSUPPORTED : LLAMA_ERR_INVALID_ARG,
                 "a tile of " + std::to_string(tile) + " records needs " + std::to_string(lds) +
@@ -448,6 +466,30 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
                 "a destination tile of " + std::to_string(tile) + " records spans more than 65536 bytes");
   S.lds_stride = lds_stride(S, (uint32_t)tile);
   D.lds_stride = lds_stride(D, (uint32_t)tile);
+  if (plan.kind == PK_RAW) {
+    // destination chunks are 16-byte runs of one column when the mapping
+    // keeps consecutive records of a column together
+    auto runs = [](const Side& x) {
+      return x.layout == LY_PLANAR || (x.layout == LY_AOSOA && (x.lanes * x.cs) % 16u == 0u);
+    };
+    Geo& g = plan.args.can;
+    std::memset(&g, 0, sizeof(g));
+    if (mode == RM_DIRECT) {
+      plan.args.colrun = (runs(D) && runs(S)) || (D.layout == LY_AOS && S.layout == LY_AOS);
+    } else {
+      plan.args.colrun = runs(D);
+      g.layout = LY_PLANAR;
+      g.cs = mode == RM_MERGE ? ES : 1u;
+      g.log2cs = log2u(g.cs);
+      g.ncols = mode == RM_MERGE ? F : F * ES;
+      g.rec_bytes = F * ES;
+      g.lanes = 1;
+      g.mb = 1;  // planes start 16-byte aligned
+      g.lds_stride = (uint32_t)(tile * g.cs + 16u);
+      g.div_L = make_div(1);
+      plan.args.can_off = (uint32_t)((tile_lds_bytes(S, (uint32_t)tile) + 15u) & ~15u);
+    }
+  }
   plan.args.tile = (uint32_t)tile;
   plan.ntiles = (src->n + tile - 1) / tile;
   if (plan.ntiles > 0xFFFFFFFFull) return fail(LLAMA_ERR_INDEX_OVERFLOW, "too many tiles");
@@ -462,7 +504,7 @@ llama_status launch_plan(const Plan& plan, hipStream_t st) {
   if (plan.ntiles == 0) return LLAMA_OK;
   hipError_t e = hipSuccess;
   switch (plan.kind) {
-    case PK_RAW: e = launch_raw(plan.args, plan.unit, plan.grid, plan.lds, st); break;
+    case PK_RAW: e = launch_raw(plan.args, plan.unit, raw_variant(plan.args, plan.unit), plan.grid, plan.lds, st); break;
     case PK_CONV: e = launch_conv(plan.args, plan.unit, plan.grid, plan.lds, st); break;
     case PK_PACK: e = launch_pack(plan.args, plan.grid, plan.lds, st); break;
     case PK_UNPACK: e = launch_unpack(plan.args, plan.unit, plan.grid, plan.lds, st); break;

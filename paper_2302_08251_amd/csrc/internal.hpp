@@ -75,6 +75,20 @@ enum Codec : uint32_t {
   CD_U8 = 0, CD_I8, CD_U16, CD_I16, CD_U32, CD_I32, CD_U64, CD_I64, CD_F32, CD_F64,
 };
 
+// Geometry of a tile image in LDS (the fields the source address function
+// reads).  For a relayout it describes the canonical planar image.
+struct Geo {
+  uint32_t layout, cs, log2cs, ncols, rec_bytes, lanes, mb, n_mod16, lds_stride, pad;
+  Div div_L;
+};
+
+// Raw-copy modes: how the source tile reaches Phase B.
+enum RawMode : uint32_t {
+  RM_DIRECT = 0,  // Phase B gathers from the verbatim source image
+  RM_MERGE = 1,   // Bytesplit source: byte columns merged into element planes first
+  RM_SPLIT = 2,   // Bytesplit destination: element columns split into byte planes first
+};
+
 struct TileArgs {
   Side src;
   Side dst;
@@ -82,6 +96,11 @@ struct TileArgs {
   uint32_t ntiles_lo;   // number of tiles (low 32 bits; tiles < 2^32)
   uint32_t conv;        // Conv
   uint32_t codec;       // Codec (pack / unpack)
+  uint32_t mode;        // RawMode
+  uint32_t colrun;      // 1: destination chunks are runs of one column (copied 16 bytes at a time)
+  uint32_t can_off;     // LDS offset of the canonical image (MERGE / SPLIT)
+  uint32_t pad;
+  Geo can;              // canonical image geometry (MERGE / SPLIT)
 };
 
 }  // namespace lm

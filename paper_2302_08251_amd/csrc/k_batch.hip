@@ -3,8 +3,9 @@
 // every view's tiles (prefix sums in `prefix`); workgroup b takes tiles
 // b, b + G, b + 2G, ... so consecutive tiles of one view spread over all
 // XCDs and every workgroup gets the same number of tiles.  The per-tile work
-// is the single-view tile engine, selected by the view's unit size with a
-// wave-uniform branch.
+// is the single-view tile engine, selected by the view's leaf size and copy
+// variant with wave-uniform branches; the host orders views by variant so
+// that a workgroup walks through one variant's tiles at a time.
 #include "batch.hpp"
 #include "kernels.hpp"
 
@@ -20,13 +21,11 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchItem* __restrict_
     const uint64_t i0 = (uint64_t)(t - prefix[v]) * it.args.tile;
     const uint64_t left = it.args.src.n - i0;
     const uint32_t nt = left < (uint64_t)it.args.tile ? (uint32_t)left : it.args.tile;
-    load_tile(it.args.src, i0, nt, lds);
-    wait_tile_loads();
     switch (it.unit) {
-      case 1: phase_b_raw<1>(it.args.src, it.args.dst, i0, nt, lds); break;
-      case 2: phase_b_raw<2>(it.args.src, it.args.dst, i0, nt, lds); break;
-      case 4: phase_b_raw<4>(it.args.src, it.args.dst, i0, nt, lds); break;
-      default: phase_b_raw<8>(it.args.src, it.args.dst, i0, nt, lds); break;
+      case 1: tile_raw_any<1>(it.args, it.variant, i0, nt, lds); break;
+      case 2: tile_raw_any<2>(it.args, it.variant, i0, nt, lds); break;
+      case 4: tile_raw_any<4>(it.args, it.variant, i0, nt, lds); break;
+      default: tile_raw_any<8>(it.args, it.variant, i0, nt, lds); break;
     }
     __syncthreads();
   }

@@ -1,14 +1,32 @@
-// Raw layout copies (no value conversion), units of 1, 2, 4 or 8 bytes.
+// Raw layout copies (no value conversion) of records with 1, 2 or 8 byte
+// leaves; 4-byte leaves are in k_raw4.hip.
 #include "kernels.hpp"
 
 namespace lm {
 
-hipError_t launch_raw(const TileArgs& a, uint32_t unit, uint32_t grid, uint32_t lds, hipStream_t st) {
-  switch (unit) {
-    case 1: return launch_k<0, 0, 1>(a, grid, lds, st);
-    case 2: return launch_k<0, 0, 2>(a, grid, lds, st);
-    case 4: return launch_k<0, 0, 4>(a, grid, lds, st);
-    case 8: return launch_k<0, 0, 8>(a, grid, lds, st);
+uint32_t raw_variant(const TileArgs& a, uint32_t leaf_bytes) {
+  if (a.mode == RM_MERGE) return RV_MERGE;
+  if (a.mode == RM_SPLIT) return RV_SPLIT;
+  return a.src.cs == leaf_bytes && leaf_bytes > 1 ? RV_DIRECT_ES : RV_DIRECT_1;
+}
+
+template <int ES>
+static hipError_t launch_es(const TileArgs& a, uint32_t rv, uint32_t grid, uint32_t lds, hipStream_t st) {
+  switch (rv) {
+    case RV_DIRECT_ES: return launch_raw_rv<ES, RV_DIRECT_ES>(a, grid, lds, st);
+    case RV_DIRECT_1: return launch_raw_rv<ES, RV_DIRECT_1>(a, grid, lds, st);
+    case RV_MERGE: return launch_raw_rv<ES, RV_MERGE>(a, grid, lds, st);
+    default: return launch_raw_rv<ES, RV_SPLIT>(a, grid, lds, st);
+  }
+}
+
+hipError_t launch_raw(const TileArgs& a, uint32_t leaf_bytes, uint32_t variant, uint32_t grid, uint32_t lds,
+                      hipStream_t st) {
+  switch (leaf_bytes) {
+    case 1: return launch_raw_rv<1, RV_DIRECT_1>(a, grid, lds, st);
+    case 2: return launch_es<2>(a, variant, grid, lds, st);
+    case 4: return launch_raw4(a, variant, grid, lds, st);
+    case 8: return launch_es<8>(a, variant, grid, lds, st);
   }
   return hipErrorInvalidValue;
 }

@@ -1,0 +1,15 @@
+// Raw layout copies of records with 4-byte leaves (f32 / i32 / u32).
+#include "kernels.hpp"
+
+namespace lm {
+
+hipError_t launch_raw4(const TileArgs& a, uint32_t variant, uint32_t grid, uint32_t lds, hipStream_t st) {
+  switch (variant) {
+    case RV_DIRECT_ES: return launch_raw_rv<4, RV_DIRECT_ES>(a, grid, lds, st);
+    case RV_DIRECT_1: return launch_raw_rv<4, RV_DIRECT_1>(a, grid, lds, st);
+    case RV_MERGE: return launch_raw_rv<4, RV_MERGE>(a, grid, lds, st);
+    default: return launch_raw_rv<4, RV_SPLIT>(a, grid, lds, st);
+  }
+}
+
+}  // namespace lm

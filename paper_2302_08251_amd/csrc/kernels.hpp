@@ -19,12 +19,83 @@ namespace lm {
     default: CALL(LY_AOSOA, LY_AOSOA); break;                   \
   }
 
-template <int U>
-__device__ __forceinline__ void phase_b_raw(const Side& s, const Side& d, uint64_t i0, uint32_t nt,
-                                            const uint8_t* lds) {
-#define LM_CALL(DL, SL) store_raw<U, DL, SL>(s, d, i0, nt, lds)
-  LM_LAYOUT_PAIRS(LM_CALL)
-#undef LM_CALL
+// Raw-copy variants: how the source tile reaches Phase B (see RawMode) and
+// the unit of Phase B.
+enum RawVariant : uint32_t {
+  RV_DIRECT_ES = 0,  // same column size on both sides: leaf elements
+  RV_DIRECT_1 = 1,   // both sides Bytesplit: bytes
+  RV_MERGE = 2,      // Bytesplit source -> element columns
+  RV_SPLIT = 3,      // element columns -> Bytesplit destination
+};
+
+// Phase B for one destination layout DL from an LDS image whose layout is
+// chosen by a wave-uniform branch.
+template <int U, int DL, int COLRUN, typename G>
+__device__ __forceinline__ void phase_b_dl(const G& s, const Side& d, uint64_t i0, uint32_t nt, const uint8_t* lds) {
+  if constexpr (COLRUN) {
+    if constexpr (DL == LY_AOS) {
+      store_colrun<U, LY_AOS, LY_AOS>(s, d, i0, nt, lds);  // same record: identical byte images
+    } else {
+      if (s.layout == LY_AOSOA) store_colrun<U, DL, LY_AOSOA>(s, d, i0, nt, lds);
+      else store_colrun<U, DL, LY_PLANAR>(s, d, i0, nt, lds);
+    }
+  } else {
+    switch (s.layout) {
+      case LY_AOS: store_raw<U, DL, LY_AOS>(s, d, i0, nt, lds); break;
+      case LY_PLANAR: store_raw<U, DL, LY_PLANAR>(s, d, i0, nt, lds); break;
+      default: store_raw<U, DL, LY_AOSOA>(s, d, i0, nt, lds); break;
+    }
+  }
+}
+
+// One tile of a raw copy of records whose leaves are ES bytes: verbatim
+// source image, an optional relayout through a canonical planar image when
+// exactly one side is a Bytesplit, then Phase B.
+template <int ES, int RV, int DL, int COLRUN>
+__device__ __forceinline__ void tile_raw(const TileArgs& a, uint64_t i0, uint32_t nt, uint8_t* lds) {
+  load_tile(a.src, i0, nt, lds);
+  wait_tile_loads();
+  if constexpr (RV == RV_MERGE || RV == RV_SPLIT) {
+    uint8_t* can = lds + a.can_off;
+    const uint32_t cst = a.can.lds_stride;
+    if constexpr (RV == RV_MERGE) {
+      if (a.src.layout == LY_AOSOA) relayout_merge<ES, LY_AOSOA>(a.src, nt, lds, can, cst);
+      else relayout_merge<ES, LY_PLANAR>(a.src, nt, lds, can, cst);
+    } else {
+      switch (a.src.layout) {
+        case LY_PLANAR: relayout_split<ES, LY_PLANAR>(a.src, nt, lds, can, cst); break;
+        case LY_AOSOA: relayout_split<ES, LY_AOSOA>(a.src, nt, lds, can, cst); break;
+        default: relayout_split<ES, LY_AOS>(a.src, nt, lds, can, cst); break;
+      }
+    }
+    __syncthreads();
+    phase_b_dl<RV == RV_MERGE ? ES : 1, DL, COLRUN>(a.can, a.dst, i0, nt, can);
+  } else {
+    phase_b_dl<RV == RV_DIRECT_ES ? ES : 1, DL, COLRUN>(a.src, a.dst, i0, nt, lds);
+  }
+}
+
+// Runtime selection of the variant (batched copies).
+template <int ES>
+__device__ __forceinline__ void tile_raw_any(const TileArgs& a, uint32_t rv, uint64_t i0, uint32_t nt, uint8_t* lds) {
+#define LM_DL(RV, DL)                                                        \
+  if (a.dst.layout == DL) {                                                  \
+    if (a.colrun) tile_raw<ES, RV, DL, 1>(a, i0, nt, lds);                   \
+    else tile_raw<ES, RV, DL, 0>(a, i0, nt, lds);                            \
+    return;                                                                  \
+  }
+#define LM_RV(RV) \
+  if (rv == RV) { LM_DL(RV, LY_AOS) LM_DL(RV, LY_PLANAR) LM_DL(RV, LY_AOSOA) }
+  if constexpr (ES == 1) {
+    LM_RV(RV_DIRECT_1)
+  } else {
+    LM_RV(RV_DIRECT_ES)
+    LM_RV(RV_DIRECT_1)
+    LM_RV(RV_MERGE)
+    LM_RV(RV_SPLIT)
+  }
+#undef LM_RV
+#undef LM_DL
 }
 
 template <int CONV, int U>
@@ -55,7 +126,21 @@ __device__ __forceinline__ void phase_b_unpack(const Side& s, const Side& d, uin
   }
 }
 
-// kind: 0 raw, 1 conversion, 2 pack, 3 unpack
+// Raw copies, one kernel per (leaf bytes, variant, destination layout,
+// column-run flag) so that each kernel holds only the Phase B bodies it runs.
+template <int ES, int RV, int DL, int COLRUN>
+__global__ __launch_bounds__(kThreads) void k_raw(const TileArgs a) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+  for (uint32_t t = blockIdx.x; t < a.ntiles_lo; t += gridDim.x) {
+    const uint64_t i0 = (uint64_t)t * a.tile;
+    const uint64_t left = a.src.n - i0;
+    const uint32_t nt = left < (uint64_t)a.tile ? (uint32_t)left : a.tile;
+    tile_raw<ES, RV, DL, COLRUN>(a, i0, nt, lds);
+    __syncthreads();
+  }
+}
+
+// kind: 1 conversion, 2 pack, 3 unpack
 template <int KIND, int P0, int U>
 __global__ __launch_bounds__(kThreads) void k_tile(const TileArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
@@ -65,8 +150,7 @@ __global__ __launch_bounds__(kThreads) void k_tile(const TileArgs a) {
     const uint32_t nt = left < (uint64_t)a.tile ? (uint32_t)left : a.tile;
     load_tile(a.src, i0, nt, lds);
     wait_tile_loads();
-    if constexpr (KIND == 0) phase_b_raw<U>(a.src, a.dst, i0, nt, lds);
-    else if constexpr (KIND == 1) phase_b_conv<P0, U>(a.src, a.dst, i0, nt, lds);
+    if constexpr (KIND == 1) phase_b_conv<P0, U>(a.src, a.dst, i0, nt, lds);
     else if constexpr (KIND == 2) phase_b_pack<P0>(a.src, a.dst, i0, nt, lds);
     else phase_b_unpack<P0, U>(a.src, a.dst, i0, nt, lds);
     __syncthreads();
@@ -74,7 +158,10 @@ __global__ __launch_bounds__(kThreads) void k_tile(const TileArgs a) {
 }
 
 // Host launchers (one per kernel family, defined in the k_*.hip files).
-hipError_t launch_raw(const TileArgs& a, uint32_t unit, uint32_t grid, uint32_t lds, hipStream_t st);
+hipError_t launch_raw(const TileArgs& a, uint32_t leaf_bytes, uint32_t variant, uint32_t grid, uint32_t lds,
+                      hipStream_t st);
+hipError_t launch_raw4(const TileArgs& a, uint32_t variant, uint32_t grid, uint32_t lds, hipStream_t st);
+uint32_t raw_variant(const TileArgs& a, uint32_t leaf_bytes);
 hipError_t launch_conv(const TileArgs& a, uint32_t unit, uint32_t grid, uint32_t lds, hipStream_t st);
 hipError_t launch_pack(const TileArgs& a, uint32_t grid, uint32_t lds, hipStream_t st);
 hipError_t launch_unpack(const TileArgs& a, uint32_t unit, uint32_t grid, uint32_t lds, hipStream_t st);
@@ -83,6 +170,21 @@ template <int KIND, int P0, int U>
 inline hipError_t launch_k(const TileArgs& a, uint32_t grid, uint32_t lds, hipStream_t st) {
   hipLaunchKernelGGL((k_tile<KIND, P0, U>), dim3(grid), dim3(kThreads), lds, st, a);
   return hipGetLastError();
+}
+
+template <int ES, int RV>
+inline hipError_t launch_raw_rv(const TileArgs& a, uint32_t grid, uint32_t lds, hipStream_t st) {
+#define LM_L(DL)                                                                                  \
+  if (a.dst.layout == DL) {                                                                       \
+    if (a.colrun) hipLaunchKernelGGL((k_raw<ES, RV, DL, 1>), dim3(grid), dim3(kThreads), lds, st, a); \
+    else hipLaunchKernelGGL((k_raw<ES, RV, DL, 0>), dim3(grid), dim3(kThreads), lds, st, a);          \
+    return hipGetLastError();                                                                     \
+  }
+  LM_L(LY_AOS)
+  LM_L(LY_PLANAR)
+  LM_L(LY_AOSOA)
+#undef LM_L
+  return hipErrorInvalidValue;
 }
 
 }  // namespace lm

@@ -83,7 +83,8 @@ __device__ __forceinline__ uint32_t seg_lds(const Side& s, uint32_t seg) {
 }
 
 // Start phase (mod 16) of planar column c of a single-blob side.
-__device__ __forceinline__ uint32_t planar_phase(const Side& s, uint32_t c) {
+template <typename G>
+__device__ __forceinline__ uint32_t planar_phase(const G& s, uint32_t c) {
   return s.mb ? 0u : ((s.n_mod16 * s.cs * c) & 15u);
 }
 
@@ -152,9 +153,9 @@ __device__ __forceinline__ void dst_inv(const Side& d, uint32_t seg, uint32_t x,
 }
 
 // Source forward: LDS offset of byte b of the stored record image of
-// tile-local record r.
-template <int SL>
-__device__ __forceinline__ uint32_t src_addr(const Side& s, uint32_t r, uint32_t b) {
+// tile-local record r (G is a Side or the Geo of a canonical image).
+template <int SL, typename G>
+__device__ __forceinline__ uint32_t src_addr(const G& s, uint32_t r, uint32_t b) {
   if constexpr (SL == LY_AOS) {
     return r * s.rec_bytes + b;
   } else if constexpr (SL == LY_PLANAR) {
@@ -243,25 +244,213 @@ __device__ __forceinline__ void for_dst_chunks(const Side& d, uint64_t i0, uint3
 // Phase B, raw copy: units of U = min(source column, destination column) bytes
 // ---------------------------------------------------------------------------
 
-template <int U, int DL, int SL>
-__device__ __forceinline__ void store_raw(const Side& s, const Side& d, uint64_t i0, uint32_t nt,
-                                          const uint8_t* lds) {
+template <int U, int DL, int SL, typename G>
+__device__ __forceinline__ void store_raw(const G& s, const Side& d, uint64_t i0, uint32_t nt,
+                                          const uint8_t* lds);
+
+// ---------------------------------------------------------------------------
+// In-LDS relayout between Bytesplit byte columns and element columns
+// (Sec. 3 Bytesplit).  Four consecutive records of one field form a 4 x ES
+// byte block.  MERGE reads the block from ES byte columns (four bytes each)
+// and writes four elements into the field's plane of a canonical planar
+// image; SPLIT reads four elements and writes ES four-byte words into the
+// byte planes.  A 4 x 4 byte block is transposed with eight v_perm_b32.
+// Consecutive lanes take consecutive blocks, so the canonical image is
+// written (MERGE, SPLIT) and the planar source read (SPLIT) without bank
+// conflicts.
+// ---------------------------------------------------------------------------
+
+// out[j] byte k = in[k] byte j
+__device__ __forceinline__ void transpose4x4(const uint32_t (&in)[4], uint32_t (&out)[4]) {
+  const uint32_t t01 = __builtin_amdgcn_perm(in[1], in[0], 0x05010400u);
+  const uint32_t t23 = __builtin_amdgcn_perm(in[3], in[2], 0x05010400u);
+  const uint32_t u01 = __builtin_amdgcn_perm(in[1], in[0], 0x07030602u);
+  const uint32_t u23 = __builtin_amdgcn_perm(in[3], in[2], 0x07030602u);
+  out[0] = __builtin_amdgcn_perm(t23, t01, 0x05040100u);
+  out[1] = __builtin_amdgcn_perm(t23, t01, 0x07060302u);
+  out[2] = __builtin_amdgcn_perm(u23, u01, 0x05040100u);
+  out[3] = __builtin_amdgcn_perm(u23, u01, 0x07060302u);
+}
+
+// bytes of byte column c for tile-local records r .. r+3 (r a multiple of 4)
+template <int SL>
+__device__ __forceinline__ uint32_t read_run4(const Side& s, const uint8_t* lds, uint32_t r, uint32_t c) {
+  const uint32_t a = src_addr<SL>(s, r, c);
+  const bool contiguous = SL == LY_PLANAR || (SL == LY_AOSOA && (s.lanes & 3u) == 0u);
+  if (contiguous && (a & 3u) == 0u) return *(const uint32_t*)(lds + a);
+  uint32_t w = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < 4; ++j) w |= (uint32_t)lds[src_addr<SL>(s, r + j, c)] << (8u * j);
+  return w;
+}
+
+// four elements (ES bytes each) of field f for records r .. r+3, as dwords:
+// e[j * ES/4 + h] is dword h of element j (ES = 4, 8); for ES = 2, e[0], e[1]
+// hold elements (0, 1) and (2, 3)
+template <int ES, int SL>
+__device__ __forceinline__ void read_elems4(const Side& s, const uint8_t* lds, uint32_t r, uint32_t f,
+                                            uint32_t (&e)[ES]) {
+  const uint32_t a = src_addr<SL>(s, r, f * ES);
+  const bool contiguous = SL == LY_PLANAR || (SL == LY_AOSOA && (s.lanes & 3u) == 0u);
+  if constexpr (ES == 2) {
+    if (contiguous && (a & 7u) == 0u) {
+      const u32x2 v = *(const u32x2*)(lds + a);
+      e[0] = v.x;
+      e[1] = v.y;
+    } else {
+      uint32_t h[4];
+#pragma unroll
+      for (uint32_t j = 0; j < 4; ++j) h[j] = *(const uint16_t*)(lds + src_addr<SL>(s, r + j, f * 2));
+      e[0] = h[0] | (h[1] << 16);
+      e[1] = h[2] | (h[3] << 16);
+    }
+  } else {
+    constexpr int DW = ES / 4;  // dwords per element
+    if (contiguous && (a & 15u) == 0u) {
+#pragma unroll
+      for (int q = 0; q < DW; ++q) {
+        const u32x4 v = *(const u32x4*)(lds + a + 16u * q);
+        e[4 * q + 0] = v.x;
+        e[4 * q + 1] = v.y;
+        e[4 * q + 2] = v.z;
+        e[4 * q + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (uint32_t j = 0; j < 4; ++j)
+#pragma unroll
+        for (int h = 0; h < DW; ++h) e[j * DW + h] = *(const uint32_t*)(lds + src_addr<SL>(s, r + j, f * ES) + 4u * h);
+    }
+  }
+}
+
+template <int ES, int SL>
+__device__ __forceinline__ void relayout_merge(const Side& s, uint32_t nt, const uint8_t* lds, uint8_t* can,
+                                               uint32_t can_stride) {
+  const uint32_t F = s.ncols / ES;
+  const uint32_t quads = (nt + 3u) >> 2;
+  const uint32_t items = F * quads;
+  for (uint32_t q = threadIdx.x; q < items; q += blockDim.x) {
+    const uint32_t f = q / quads;
+    const uint32_t r = (q - f * quads) * 4u;
+    uint8_t* out = can + f * can_stride + r * ES;
+    if constexpr (ES == 2) {
+      const uint32_t b0 = read_run4<SL>(s, lds, r, 2 * f), b1 = read_run4<SL>(s, lds, r, 2 * f + 1);
+      u32x2 v = {__builtin_amdgcn_perm(b1, b0, 0x05010400u), __builtin_amdgcn_perm(b1, b0, 0x07030602u)};
+      *(u32x2*)out = v;
+    } else {
+#pragma unroll
+      for (int h = 0; h < ES / 4; ++h) {  // bytes 4h .. 4h+3 of the elements
+        uint32_t in[4], o[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) in[k] = read_run4<SL>(s, lds, r, f * ES + 4 * h + k);
+        transpose4x4(in, o);
+        if constexpr (ES == 4) {
+          *(u32x4*)out = u32x4{o[0], o[1], o[2], o[3]};
+        } else {  // ES == 8: element j = (dword 0, dword 1)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) *(uint32_t*)(out + 8 * j + 4 * h) = o[j];
+        }
+      }
+    }
+  }
+}
+
+template <int ES, int SL>
+__device__ __forceinline__ void relayout_split(const Side& s, uint32_t nt, const uint8_t* lds, uint8_t* can,
+                                               uint32_t can_stride) {
+  const uint32_t F = s.ncols;
+  const uint32_t quads = (nt + 3u) >> 2;
+  const uint32_t items = F * quads;
+  for (uint32_t q = threadIdx.x; q < items; q += blockDim.x) {
+    const uint32_t f = q / quads;
+    const uint32_t r = (q - f * quads) * 4u;
+    uint32_t e[ES];
+    read_elems4<ES, SL>(s, lds, r, f, e);
+    uint8_t* out = can + (f * ES) * can_stride + r;
+    if constexpr (ES == 2) {
+      *(uint32_t*)out = __builtin_amdgcn_perm(e[1], e[0], 0x06040200u);
+      *(uint32_t*)(out + can_stride) = __builtin_amdgcn_perm(e[1], e[0], 0x07050301u);
+    } else {
+      constexpr int DW = ES / 4;
+#pragma unroll
+      for (int h = 0; h < DW; ++h) {
+        uint32_t in[4], o[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) in[j] = e[j * DW + h];
+        transpose4x4(in, o);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) *(uint32_t*)(out + (4 * h + k) * can_stride) = o[k];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Phase B over column runs: when every destination chunk holds 16/cs
+// consecutive records of one column and the source keeps those records
+// contiguous too (planar, or AoSoA with 16-byte column runs), a chunk is one
+// LDS read and one 128-bit store.  Other chunks take the unit-by-unit path.
+// ---------------------------------------------------------------------------
+
+template <int U, int DL, int SL, typename G>
+__device__ __forceinline__ void raw_chunk(const G& s, const Side& d, uint32_t nt, const uint8_t* lds,
+                                          __amdgpu_buffer_rsrc_t rs, uint32_t seg, uint32_t off, int x0,
+                                          uint32_t len) {
   constexpr int NU = 16 / U;
   constexpr uint32_t FULL = (1u << NU) - 1u;
-  for_dst_chunks(d, i0, nt, [&](__amdgpu_buffer_rsrc_t rs, uint32_t seg, uint32_t off, int x0, uint32_t len) {
-    uint32_t w[4] = {0u, 0u, 0u, 0u};
-    uint32_t valid = 0;
+  uint32_t w[4] = {0u, 0u, 0u, 0u};
+  uint32_t valid = 0;
 #pragma unroll
-    for (int t = 0; t < NU; ++t) {
-      const int x = x0 + t * U;
-      bool ok = x >= 0 && x < (int)len;
+  for (int t = 0; t < NU; ++t) {
+    const int x = x0 + t * U;
+    bool ok = x >= 0 && x < (int)len;
+    uint32_t r, b;
+    dst_inv<DL>(d, seg, ok ? (uint32_t)x : 0u, r, b);
+    ok = ok && r < nt;
+    if (ok) put_unit<U>(w, t, lds_read<U>(lds, src_addr<SL>(s, r, b)));
+    valid |= (uint32_t)ok << t;
+  }
+  store_chunk<U>(rs, off, w, valid, FULL);
+}
+
+template <int U, int DL, int SL, typename G>
+__device__ __forceinline__ void store_raw(const G& s, const Side& d, uint64_t i0, uint32_t nt,
+                                          const uint8_t* lds) {
+  for_dst_chunks(d, i0, nt, [&](__amdgpu_buffer_rsrc_t rs, uint32_t seg, uint32_t off, int x0, uint32_t len) {
+    raw_chunk<U, DL, SL>(s, d, nt, lds, rs, seg, off, x0, len);
+  });
+}
+
+template <int U, int DL, int SL, typename G>
+__device__ __forceinline__ void store_colrun(const G& s, const Side& d, uint64_t i0, uint32_t nt,
+                                             const uint8_t* lds) {
+  constexpr uint32_t NREC = 16 / U;
+  for_dst_chunks(d, i0, nt, [&](__amdgpu_buffer_rsrc_t rs, uint32_t seg, uint32_t off, int x0, uint32_t len) {
+    if (x0 >= 0 && x0 + 16 <= (int)len) {
       uint32_t r, b;
-      dst_inv<DL>(d, seg, ok ? (uint32_t)x : 0u, r, b);
-      ok = ok && r < nt;
-      if (ok) put_unit<U>(w, t, lds_read<U>(lds, src_addr<SL>(s, r, b)));
-      valid |= (uint32_t)ok << t;
+      dst_inv<DL>(d, seg, (uint32_t)x0, r, b);
+      if (r + NREC <= nt) {
+        const uint32_t a = src_addr<SL>(s, r, b);
+        if (src_addr<SL>(s, r + NREC - 1u, b) - a == 16u - U) {
+          u32x4 v;
+          if ((a & 15u) == 0u) {
+            v = *(const u32x4*)(lds + a);
+          } else if ((a & 3u) == 0u) {
+            const uint32_t* p = (const uint32_t*)(lds + a);
+            v = u32x4{p[0], p[1], p[2], p[3]};
+          } else {
+            uint32_t t[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (uint32_t k = 0; k < 16; ++k) t[k >> 2] |= (uint32_t)lds[a + k] << (8u * (k & 3u));
+            v = u32x4{t[0], t[1], t[2], t[3]};
+          }
+          __builtin_amdgcn_raw_buffer_store_b128(v, rs, off, 0, 0);
+          return;
+        }
+      }
     }
-    store_chunk<U>(rs, off, w, valid, FULL);
+    raw_chunk<U, DL, SL>(s, d, nt, lds, rs, seg, off, x0, len);
   });
 }
 
@@ -464,8 +653,12 @@ __device__ __forceinline__ void store_conv(const Side& s, const Side& d, uint64_
 }
 
 // ---------------------------------------------------------------------------
-// Phase B, pack into bit streams: each lane assembles four 32-bit words of
-// one field's stream from the values whose bits they hold.
+// Phase B, pack into bit streams.  A wave owns 256 consecutive words of one
+// field's stream; lane l assembles words l, l+64, l+128, l+192 from the codes
+// of the values whose bits they hold.  Neighbouring lanes thus read
+// neighbouring values from LDS (no bank conflicts for any code width) and
+// every store instruction writes 256 contiguous bytes.  Each lane owns whole
+// words, so no two lanes write the same word.
 // ---------------------------------------------------------------------------
 
 template <int CODEC, int SL>
@@ -473,32 +666,34 @@ __device__ __forceinline__ void store_pack(const Side& s, const Side& d, uint64_
                                            const uint8_t* lds) {
   constexpr int ES = CodecInfo<CODEC>::ES;
   const uint32_t B = d.bits;
-  for_dst_chunks(d, i0, nt, [&](__amdgpu_buffer_rsrc_t rs, uint32_t f, uint32_t off, int x0, uint32_t len) {
-    uint32_t w[4];
-    uint32_t valid = 0;
+  const SegGeo g = seg_geo(d, nt);
+  const uint32_t words = g.len >> 2;
+  const uint32_t gps = (words + 255u) >> 8;
+  const uint32_t items = g.nseg * gps;
+  const uint32_t w0 = wave_id(), nw = num_waves(), lane = lane_id();
+  for (uint32_t it = w0; it < items; it += nw) {
+    const uint32_t f = it / gps;
+    const uint32_t grp = it - f * gps;
+    const uint64_t start = seg_start(d, f, i0);  // 16-byte aligned: tiles are multiples of 128 records
+    const auto rs = make_rsrc((const uint8_t*)seg_blob(d, f) + start, d.blob_size - start);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint32_t wi = (uint32_t)x0 / 4u + q;  // tile-local word index (segments start 16-aligned)
-      const bool ok = wi * 4u < len;
-      uint32_t acc = 0;
-      if (ok) {
-        const uint32_t bit0 = wi * 32u;
-        uint32_t r = fdiv(bit0, d.div_B);
-        const uint32_t first = bit0 - r * B;
-        acc = encode<CODEC>(fetch_elem<ES, SL>(s, lds, r, f), d) >> first;
-        uint32_t nb = B - first;
+    for (uint32_t q = 0; q < 4; ++q) {
+      const uint32_t wi = grp * 256u + q * 64u + lane;  // tile-local word index
+      if (wi >= words) continue;
+      const uint32_t bit0 = wi * 32u;
+      uint32_t r = fdiv(bit0, d.div_B);
+      const uint32_t first = bit0 - r * B;
+      uint32_t acc = encode<CODEC>(fetch_elem<ES, SL>(s, lds, r, f), d) >> first;
+      uint32_t nb = B - first;
+      ++r;
+      while (nb < 32u && r < nt) {
+        acc |= encode<CODEC>(fetch_elem<ES, SL>(s, lds, r, f), d) << nb;
+        nb += B;
         ++r;
-        while (nb < 32u && r < nt) {
-          acc |= encode<CODEC>(fetch_elem<ES, SL>(s, lds, r, f), d) << nb;
-          nb += B;
-          ++r;
-        }
       }
-      w[q] = acc;
-      valid |= (uint32_t)ok << q;
+      __builtin_amdgcn_raw_buffer_store_b32(acc, rs, wi * 4u, 0, 0);
     }
-    store_chunk<4>(rs, off, w, valid, 0xFu);
-  });
+  }
 }
 
 // ---------------------------------------------------------------------------
