@@ -206,7 +206,8 @@ llama_status llama_batch_launch(llama_batch* batch, void* stream);
 llama_status llama_batch_launch_per_view(llama_batch* batch, void* stream);
 typedef struct llama_batch_info {
   uint32_t n_views;
-  uint32_t tile_records;     /* chosen tile size                               */
+  uint32_t tile_records;     /* chosen tile size (0: each view's default tile,
+                                1: the same capped to 16 KiB of LDS)            */
   uint32_t grid;             /* persistent workgroups                          */
   uint64_t total_tiles;
   uint64_t algorithmic_bytes;/* mapped bytes read + mapped bytes written       */

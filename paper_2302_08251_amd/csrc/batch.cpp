@@ -62,8 +62,10 @@ llama_status build_items(llama_batch* b, uint32_t T, std::vector<BatchItem>& ite
   lds = 0;
   for (size_t v = 0; v < n; ++v) {
     Plan p;
-    llama_launch_params lp{T, 0};
-    llama_status st = plan_copy(b->srcs[v], b->dsts[v], &lp, p);
+    // T = 0: each view's default tile; T = 1: the same, capped to 16 KiB of
+    // LDS so that one kernel keeps full occupancy for every view
+    llama_launch_params lp{T > 1 ? T : 0u, 0};
+    llama_status st = plan_copy(b->srcs[v], b->dsts[v], &lp, p, T == 1 ? 16384u : 0u);
     if (st != LLAMA_OK) return st;
     if (p.kind != PK_RAW) return fail(LLAMA_ERR_UNSUPPORTED, "batched copies move physical layouts only");
     plans[v] = BatchItem{};
@@ -119,7 +121,7 @@ llama_status capture(llama_batch* b) {
   b->graph = nullptr;
   if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
     return hip_fail(e, "hipStreamBeginCapture");
-  hipError_t le = launch_batch(b->d_items, b->d_prefix, (uint32_t)b->total_tiles, b->grid, b->lds, b->cap);
+  hipError_t le = launch_batch(b->d_items, b->d_prefix, (uint32_t)b->total_tiles, (uint32_t)b->srcs.size(), b->grid, b->lds, b->cap);
   e = hipStreamEndCapture(b->cap, &b->graph);
   if (le != hipSuccess) return hip_fail(le, "batched launch");
   if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
@@ -197,9 +199,9 @@ bool cache_lookup(const char* path, const std::string& key, uint32_t& T, uint32_
     p = s.find(':', p);
     if (p == std::string::npos) return false;
     out = (uint32_t)std::strtoul(s.c_str() + p + 1, nullptr, 10);
-    return out > 0;
+    return true;
   };
-  return num("tile_records", T) && num("grid", G) && num("per_view_tile", P);
+  return num("tile_records", T) && num("grid", G) && num("per_view_tile", P) && G > 0;
 }
 
 void cache_store(const char* path, const std::string& key, uint32_t T, uint32_t G, uint32_t P) {
@@ -229,19 +231,20 @@ llama_status autotune(llama_batch* b, uint64_t granule, uint32_t& bestT, uint32_
   int dev = 0, cus = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  std::vector<uint32_t> tiles;
-  for (uint32_t T : {256u, 512u, 1024u, 2048u})
+  // tile candidates: 0 (each view's default tile), 1 (default tile capped to
+  // 16 KiB of LDS) and fixed sizes
+  std::vector<uint32_t> tiles = {0u, 1u};
+  for (uint32_t T : {512u, 1024u})
     if (T % granule == 0) tiles.push_back(T);
-  if (tiles.empty()) tiles.push_back((uint32_t)granule);
   double best = 1e30, best_pv = 1e30;
   bestT = bestG = bestP = 0;
   for (uint32_t T : tiles) {
     if (upload(b, T) != LLAMA_OK) continue;  // e.g. a tile that does not fit in LDS
-    for (uint32_t mult : {4u, 8u, 16u, 32u}) {
-      const uint32_t G = (uint32_t)std::min<uint64_t>((uint64_t)cus * mult, b->total_tiles);
+    for (uint32_t mult : {8u, 32u, 128u, 0u}) {  // 0: one workgroup per tile
+      const uint32_t G = (uint32_t)std::min<uint64_t>(mult ? (uint64_t)cus * mult : b->total_tiles, b->total_tiles);
       hipError_t le = hipSuccess;
       auto run = [&]() {
-        hipError_t e = launch_batch(b->d_items, b->d_prefix, (uint32_t)b->total_tiles, G, b->lds, b->cap);
+        hipError_t e = launch_batch(b->d_items, b->d_prefix, (uint32_t)b->total_tiles, (uint32_t)b->srcs.size(), G, b->lds, b->cap);
         if (e != hipSuccess) le = e;
       };
       run();
@@ -254,7 +257,7 @@ llama_status autotune(llama_batch* b, uint64_t granule, uint32_t& bestT, uint32_
       }
     }
     std::vector<Plan> pv;
-    if (per_view_plans(b, T, pv) != LLAMA_OK) continue;
+    if (T == 1 || per_view_plans(b, T, pv) != LLAMA_OK) continue;  // per-view launches need no cap
     auto run_pv = [&]() {
       for (auto& p : pv) (void)launch_plan(p, b->cap);
     };
@@ -265,7 +268,7 @@ llama_status autotune(llama_batch* b, uint64_t granule, uint32_t& bestT, uint32_
       bestP = T;
     }
   }
-  if (!bestT || !bestP) return fail(LLAMA_ERR_UNSUPPORTED, "no tile size fits every view of the batch");
+  if (!bestG) return fail(LLAMA_ERR_UNSUPPORTED, "no tile size fits every view of the batch");
   return LLAMA_OK;
 }
 

@@ -13,7 +13,7 @@ struct BatchItem {
   uint32_t pad[2];
 };
 
-hipError_t launch_batch(const BatchItem* items, const uint32_t* prefix, uint32_t total_tiles, uint32_t grid,
-                        uint32_t lds, hipStream_t st);
+hipError_t launch_batch(const BatchItem* items, const uint32_t* prefix, uint32_t total_tiles, uint32_t n_views,
+                        uint32_t grid, uint32_t lds, hipStream_t st);
 
 }  // namespace lm

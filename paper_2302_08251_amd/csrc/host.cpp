@@ -389,7 +389,7 @@ static Codec codec_of(llama_scalar t) {
 }
 
 llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama_launch_params* p,
-                       Plan& plan) {
+                       Plan& plan, uint32_t lds_cap) {
   if (!src || !dst) return fail(LLAMA_ERR_INVALID_ARG, "view is NULL");
   if (src->rec != dst->rec) return fail(LLAMA_ERR_RECORD_MISMATCH, "source and destination records differ");
   if (src->n != dst->n) return fail(LLAMA_ERR_RECORD_MISMATCH, "source and destination record counts differ");
@@ -416,6 +416,20 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     plan.kind = PK_RAW;
     plan.unit = S.es;  // leaf bytes
     plan.args.mode = S.cs == D.cs ? RM_DIRECT : (S.cs == 1 ? RM_MERGE : RM_SPLIT);
+    // fused relayout: the destination keeps runs of 4 records per column,
+    // 4-byte aligned (split: byte columns) or aligned to the store width
+    // (merge: element columns)
+    const uint64_t n = src->n;
+    if (plan.args.mode == RM_SPLIT) {
+      const bool ok = (D.layout == LY_PLANAR && (D.mb || n % 4 == 0)) || (D.layout == LY_AOSOA && D.lanes % 4 == 0);
+      if (ok) plan.args.mode = RM_SPLIT_FUSED;
+    } else if (plan.args.mode == RM_MERGE) {
+      const uint64_t A = D.es >= 4 ? 16 : 4 * D.es;  // store width of 4 elements (up to 16 bytes)
+      const bool ok = (D.layout == LY_PLANAR && (D.mb || (n * D.es) % A == 0)) ||
+                      (D.layout == LY_AOSOA && D.lanes % 4 == 0 && ((uint64_t)D.lanes * D.rec_bytes) % A == 0 &&
+                       ((uint64_t)D.lanes * D.es) % A == 0);
+      if (ok) plan.args.mode = RM_MERGE_FUSED;
+    }
   } else if (S.vkind == VK_CONV && D.vkind == VK_CONV) {
     return fail(LLAMA_ERR_UNSUPPORTED, "copy between two ChangeType views with conversions");
   } else {
@@ -428,6 +442,7 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     else return fail(LLAMA_ERR_UNSUPPORTED, "the GPU path converts between F64 and F32 only");
   }
   const uint32_t mode = plan.kind == PK_RAW ? plan.args.mode : RM_DIRECT;
+  const bool canonical = mode == RM_MERGE || mode == RM_SPLIT;
   // canonical planar image of a relayout: element planes (MERGE) or byte planes (SPLIT)
   const uint32_t F = (uint32_t)src->rec.size(), ES = S.es;
   auto can_bytes = [&](uint64_t t) -> uint64_t {
@@ -437,7 +452,7 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
   };
   auto lds_total = [&](uint64_t t) -> uint64_t {
     const uint64_t a = tile_lds_bytes(S, (uint32_t)t);
-    return mode == RM_DIRECT ? a : ((a + 15u) & ~15ull) + can_bytes(t);
+    return canonical ? ((a + 15u) & ~15ull) + can_bytes(t) : a;
   };
   const uint64_t gran = tile_granule(S, D);
   // bytes of one destination tile segment set: the destination inverse
@@ -448,11 +463,15 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
   if (tile) {
     if (tile % gran) return fail(LLAMA_ERR_INVALID_ARG, "tile_records must be a multiple of " + std::to_string(gran));
   } else {
-    // about 16 KiB per tile image on the larger side (32 KiB with a relayout)
-    const uint64_t target = mode == RM_DIRECT ? 16384 : 32768;
+    // about 16 KiB per tile image on the larger side (32 KiB with two images).
+    // Byte planes (a planar Bytesplit side) need longer tiles to fill whole
+    // 1 KiB wave groups: about 28 KiB with one such side, 21 KiB with two.
+    const bool bs = S.layout == LY_PLANAR && S.cs == 1, bd = D.layout == LY_PLANAR && D.cs == 1;
+    const uint64_t target = canonical ? 32768 : (bs && bd) ? 21504 : (bs || bd) ? 28672 : 16384;
     uint64_t per = std::max<uint64_t>(lds_total(gran), gran * dst_bytes);
     uint64_t k = per ? (target / per) : 1;
     if (k < 1) k = 1;
+    while (lds_cap && k > 1 && lds_total(gran * k) > lds_cap) --k;
     tile = gran * k;
   }
   if (tile > 65536) return fail(LLAMA_ERR_INVALID_ARG, "tile_records must be <= 65536");
@@ -476,7 +495,7 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     std::memset(&g, 0, sizeof(g));
     if (mode == RM_DIRECT) {
       plan.args.colrun = (runs(D) && runs(S)) || (D.layout == LY_AOS && S.layout == LY_AOS);
-    } else {
+    } else if (canonical) {
       plan.args.colrun = runs(D);
       g.layout = LY_PLANAR;
       g.cs = mode == RM_MERGE ? ES : 1u;
@@ -484,7 +503,10 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
       g.ncols = mode == RM_MERGE ? F : F * ES;
       g.rec_bytes = F * ES;
       g.lanes = 1;
-      g.mb = 1;  // planes start 16-byte aligned
+      // the canonical planes take the destination planes' start phase
+      // (mod 16), so that Phase B moves aligned 16-byte chunks
+      g.mb = D.layout == LY_PLANAR ? D.mb : 1u;
+      g.n_mod16 = D.n_mod16;
       g.lds_stride = (uint32_t)(tile * g.cs + 16u);
       g.div_L = make_div(1);
       plan.args.can_off = (uint32_t)((tile_lds_bytes(S, (uint32_t)tile) + 15u) & ~15u);
@@ -495,7 +517,7 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
   if (plan.ntiles > 0xFFFFFFFFull) return fail(LLAMA_ERR_INDEX_OVERFLOW, "too many tiles");
   plan.args.ntiles_lo = (uint32_t)plan.ntiles;
   plan.grid = (p && p->grid) ? (uint32_t)(p->grid < plan.ntiles ? p->grid : plan.ntiles) : (uint32_t)plan.ntiles;
-  plan.lds = (uint32_t)lds;
+  plan.lds = (uint32_t)((lds + 15u) & ~15ull);  // whole 16-byte units: funnel-shift reads may touch the last one
   plan.alg_bytes = mapped_bytes(src->rec, src->map, src->n) + mapped_bytes(dst->rec, dst->map, dst->n);
   return LLAMA_OK;
 }

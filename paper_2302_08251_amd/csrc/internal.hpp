@@ -87,6 +87,8 @@ enum RawMode : uint32_t {
   RM_DIRECT = 0,  // Phase B gathers from the verbatim source image
   RM_MERGE = 1,   // Bytesplit source: byte columns merged into element planes first
   RM_SPLIT = 2,   // Bytesplit destination: element columns split into byte planes first
+  RM_MERGE_FUSED = 3,  // as RM_MERGE, transposed in registers and stored directly
+  RM_SPLIT_FUSED = 4,  // as RM_SPLIT, transposed in registers and stored directly
 };
 
 struct TileArgs {

@@ -12,11 +12,28 @@
 namespace lm {
 
 __global__ __launch_bounds__(kThreads) void k_batch(const BatchItem* __restrict__ items,
-                                                   const uint32_t* __restrict__ prefix, uint32_t total_tiles) {
+                                                   const uint32_t* __restrict__ prefix, uint32_t total_tiles,
+                                                   uint32_t n_views) {
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   uint32_t v = 0;
   for (uint32_t t = blockIdx.x; t < total_tiles; t += gridDim.x) {
-    while (prefix[v + 1] <= t) ++v;  // tiles are visited in increasing order
+    // view holding tile t: prefix[v] <= t < prefix[v + 1].  Tiles are visited
+    // in increasing order, so gallop forward from the last view, then bisect.
+    if (prefix[v + 1] <= t) {
+      uint32_t step = 1, lo = v + 1, hi = v + 1;
+      while (hi < n_views && prefix[hi + 1] <= t) {
+        lo = hi + 1;
+        hi = hi + step;
+        step *= 2;
+        if (hi >= n_views) hi = n_views - 1;
+      }
+      while (lo < hi) {  // smallest u in [lo, hi] with prefix[u + 1] > t
+        const uint32_t mid = (lo + hi) >> 1;
+        if (prefix[mid + 1] <= t) lo = mid + 1;
+        else hi = mid;
+      }
+      v = lo;
+    }
     const BatchItem& it = items[v];
     const uint64_t i0 = (uint64_t)(t - prefix[v]) * it.args.tile;
     const uint64_t left = it.args.src.n - i0;
@@ -31,9 +48,9 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchItem* __restrict_
   }
 }
 
-hipError_t launch_batch(const BatchItem* items, const uint32_t* prefix, uint32_t total_tiles, uint32_t grid,
-                        uint32_t lds, hipStream_t st) {
-  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kThreads), lds, st, items, prefix, total_tiles);
+hipError_t launch_batch(const BatchItem* items, const uint32_t* prefix, uint32_t total_tiles, uint32_t n_views,
+                        uint32_t grid, uint32_t lds, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kThreads), lds, st, items, prefix, total_tiles, n_views);
   return hipGetLastError();
 }
 

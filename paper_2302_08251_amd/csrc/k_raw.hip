@@ -7,6 +7,8 @@ namespace lm {
 uint32_t raw_variant(const TileArgs& a, uint32_t leaf_bytes) {
   if (a.mode == RM_MERGE) return RV_MERGE;
   if (a.mode == RM_SPLIT) return RV_SPLIT;
+  if (a.mode == RM_MERGE_FUSED) return RV_MERGE_FUSED;
+  if (a.mode == RM_SPLIT_FUSED) return RV_SPLIT_FUSED;
   return a.src.cs == leaf_bytes && leaf_bytes > 1 ? RV_DIRECT_ES : RV_DIRECT_1;
 }
 
@@ -16,7 +18,9 @@ static hipError_t launch_es(const TileArgs& a, uint32_t rv, uint32_t grid, uint3
     case RV_DIRECT_ES: return launch_raw_rv<ES, RV_DIRECT_ES>(a, grid, lds, st);
     case RV_DIRECT_1: return launch_raw_rv<ES, RV_DIRECT_1>(a, grid, lds, st);
     case RV_MERGE: return launch_raw_rv<ES, RV_MERGE>(a, grid, lds, st);
-    default: return launch_raw_rv<ES, RV_SPLIT>(a, grid, lds, st);
+    case RV_SPLIT: return launch_raw_rv<ES, RV_SPLIT>(a, grid, lds, st);
+    case RV_SPLIT_FUSED: return launch_raw_fused<ES, RV_SPLIT_FUSED>(a, grid, lds, st);
+    default: return launch_raw_fused<ES, RV_MERGE_FUSED>(a, grid, lds, st);
   }
 }
 

@@ -8,7 +8,9 @@ hipError_t launch_raw4(const TileArgs& a, uint32_t variant, uint32_t grid, uint3
     case RV_DIRECT_ES: return launch_raw_rv<4, RV_DIRECT_ES>(a, grid, lds, st);
     case RV_DIRECT_1: return launch_raw_rv<4, RV_DIRECT_1>(a, grid, lds, st);
     case RV_MERGE: return launch_raw_rv<4, RV_MERGE>(a, grid, lds, st);
-    default: return launch_raw_rv<4, RV_SPLIT>(a, grid, lds, st);
+    case RV_SPLIT: return launch_raw_rv<4, RV_SPLIT>(a, grid, lds, st);
+    case RV_SPLIT_FUSED: return launch_raw_fused<4, RV_SPLIT_FUSED>(a, grid, lds, st);
+    default: return launch_raw_fused<4, RV_MERGE_FUSED>(a, grid, lds, st);
   }
 }
 

@@ -26,6 +26,8 @@ enum RawVariant : uint32_t {
   RV_DIRECT_1 = 1,   // both sides Bytesplit: bytes
   RV_MERGE = 2,      // Bytesplit source -> element columns
   RV_SPLIT = 3,      // element columns -> Bytesplit destination
+  RV_SPLIT_FUSED = 4,  // RV_SPLIT without the canonical image
+  RV_MERGE_FUSED = 5,  // RV_MERGE without the canonical image
 };
 
 // Phase B for one destination layout DL from an LDS image whose layout is
@@ -55,17 +57,25 @@ template <int ES, int RV, int DL, int COLRUN>
 __device__ __forceinline__ void tile_raw(const TileArgs& a, uint64_t i0, uint32_t nt, uint8_t* lds) {
   load_tile(a.src, i0, nt, lds);
   wait_tile_loads();
-  if constexpr (RV == RV_MERGE || RV == RV_SPLIT) {
+  if constexpr (RV == RV_SPLIT_FUSED) {
+    switch (a.src.layout) {
+      case LY_PLANAR: store_split_fused<ES, LY_PLANAR, DL>(a.src, a.dst, i0, nt, lds); break;
+      case LY_AOSOA: store_split_fused<ES, LY_AOSOA, DL>(a.src, a.dst, i0, nt, lds); break;
+      default: store_split_fused<ES, LY_AOS, DL>(a.src, a.dst, i0, nt, lds); break;
+    }
+  } else if constexpr (RV == RV_MERGE_FUSED) {
+    if (a.src.layout == LY_AOSOA) store_merge_fused<ES, LY_AOSOA, DL>(a.src, a.dst, i0, nt, lds);
+    else store_merge_fused<ES, LY_PLANAR, DL>(a.src, a.dst, i0, nt, lds);
+  } else if constexpr (RV == RV_MERGE || RV == RV_SPLIT) {
     uint8_t* can = lds + a.can_off;
-    const uint32_t cst = a.can.lds_stride;
     if constexpr (RV == RV_MERGE) {
-      if (a.src.layout == LY_AOSOA) relayout_merge<ES, LY_AOSOA>(a.src, nt, lds, can, cst);
-      else relayout_merge<ES, LY_PLANAR>(a.src, nt, lds, can, cst);
+      if (a.src.layout == LY_AOSOA) relayout_merge<ES, LY_AOSOA>(a.src, nt, lds, can, a.can);
+      else relayout_merge<ES, LY_PLANAR>(a.src, nt, lds, can, a.can);
     } else {
       switch (a.src.layout) {
-        case LY_PLANAR: relayout_split<ES, LY_PLANAR>(a.src, nt, lds, can, cst); break;
-        case LY_AOSOA: relayout_split<ES, LY_AOSOA>(a.src, nt, lds, can, cst); break;
-        default: relayout_split<ES, LY_AOS>(a.src, nt, lds, can, cst); break;
+        case LY_PLANAR: relayout_split<ES, LY_PLANAR>(a.src, nt, lds, can, a.can); break;
+        case LY_AOSOA: relayout_split<ES, LY_AOSOA>(a.src, nt, lds, can, a.can); break;
+        default: relayout_split<ES, LY_AOS>(a.src, nt, lds, can, a.can); break;
       }
     }
     __syncthreads();
@@ -86,6 +96,12 @@ __device__ __forceinline__ void tile_raw_any(const TileArgs& a, uint32_t rv, uin
   }
 #define LM_RV(RV) \
   if (rv == RV) { LM_DL(RV, LY_AOS) LM_DL(RV, LY_PLANAR) LM_DL(RV, LY_AOSOA) }
+#define LM_RVF(RV) \
+  if (rv == RV) {                                                            \
+    if (a.dst.layout == LY_AOSOA) tile_raw<ES, RV, LY_AOSOA, 0>(a, i0, nt, lds); \
+    else tile_raw<ES, RV, LY_PLANAR, 0>(a, i0, nt, lds);                     \
+    return;                                                                  \
+  }
   if constexpr (ES == 1) {
     LM_RV(RV_DIRECT_1)
   } else {
@@ -93,7 +109,10 @@ __device__ __forceinline__ void tile_raw_any(const TileArgs& a, uint32_t rv, uin
     LM_RV(RV_DIRECT_1)
     LM_RV(RV_MERGE)
     LM_RV(RV_SPLIT)
+    LM_RVF(RV_SPLIT_FUSED)
+    LM_RVF(RV_MERGE_FUSED)
   }
+#undef LM_RVF
 #undef LM_RV
 #undef LM_DL
 }
@@ -169,6 +188,13 @@ hipError_t launch_unpack(const TileArgs& a, uint32_t unit, uint32_t grid, uint32
 template <int KIND, int P0, int U>
 inline hipError_t launch_k(const TileArgs& a, uint32_t grid, uint32_t lds, hipStream_t st) {
   hipLaunchKernelGGL((k_tile<KIND, P0, U>), dim3(grid), dim3(kThreads), lds, st, a);
+  return hipGetLastError();
+}
+
+template <int ES, int RV>
+inline hipError_t launch_raw_fused(const TileArgs& a, uint32_t grid, uint32_t lds, hipStream_t st) {
+  if (a.dst.layout == LY_AOSOA) hipLaunchKernelGGL((k_raw<ES, RV, LY_AOSOA, 0>), dim3(grid), dim3(kThreads), lds, st, a);
+  else hipLaunchKernelGGL((k_raw<ES, RV, LY_PLANAR, 0>), dim3(grid), dim3(kThreads), lds, st, a);
   return hipGetLastError();
 }
 

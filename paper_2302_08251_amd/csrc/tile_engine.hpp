@@ -26,6 +26,7 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) void lds_void;
 
 constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit format, gfx9 family
+constexpr int kStoreNT = 2;             // cache policy: non-temporal (streaming) store
 
 __device__ __forceinline__ uint32_t wave_id() {
   return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -182,10 +183,21 @@ __device__ __forceinline__ uint64_t lds_read(const uint8_t* lds, uint32_t a) {
 template <int U>
 __device__ __forceinline__ void store_chunk(__amdgpu_buffer_rsrc_t rs, uint32_t off, const uint32_t (&w)[4],
                                             uint32_t valid, uint32_t full_mask) {
+  // full chunk: one 128-bit store; partial: whole dwords, then single units
   if (valid == full_mask) {
     u32x4 v = {w[0], w[1], w[2], w[3]};
-    __builtin_amdgcn_raw_buffer_store_b128(v, rs, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(v, rs, off, 0, kStoreNT);
     return;
+  }
+  if constexpr (U < 4) {
+    // dwords whose units are all valid go out whole
+    constexpr uint32_t PER = 4 / U, M = (1u << PER) - 1u;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (((valid >> (q * PER)) & M) == M) __builtin_amdgcn_raw_buffer_store_b32(w[q], rs, off + 4u * q, 0, 0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (((valid >> (q * PER)) & M) == M) valid &= ~(M << (q * PER));
   }
 #pragma unroll
   for (int t = 0; t < 16 / U; ++t) {
@@ -277,7 +289,13 @@ template <int SL>
 __device__ __forceinline__ uint32_t read_run4(const Side& s, const uint8_t* lds, uint32_t r, uint32_t c) {
   const uint32_t a = src_addr<SL>(s, r, c);
   const bool contiguous = SL == LY_PLANAR || (SL == LY_AOSOA && (s.lanes & 3u) == 0u);
-  if (contiguous && (a & 3u) == 0u) return *(const uint32_t*)(lds + a);
+  if (contiguous) {
+    if ((a & 3u) == 0u) return *(const uint32_t*)(lds + a);
+    // a misaligned run (plane start not 4-byte aligned): two aligned dwords
+    // (inside the plane's 16-byte slack) and a byte funnel shift
+    const uint32_t al = a & ~3u;
+    return __builtin_amdgcn_alignbyte(*(const uint32_t*)(lds + al + 4u), *(const uint32_t*)(lds + al), a & 3u);
+  }
   uint32_t w = 0;
 #pragma unroll
   for (uint32_t j = 0; j < 4; ++j) w |= (uint32_t)lds[src_addr<SL>(s, r + j, c)] << (8u * j);
@@ -324,41 +342,66 @@ __device__ __forceinline__ void read_elems4(const Side& s, const uint8_t* lds, u
   }
 }
 
+// write NB bytes (dwords w[]) to LDS offset a, with the widest accesses its
+// alignment allows
+template <int NB>
+__device__ __forceinline__ void lds_write(uint8_t* lds, uint32_t a, const uint32_t* w) {
+  if constexpr (NB >= 16) {
+    if ((a & 15u) == 0u) {
+#pragma unroll
+      for (int q = 0; q < NB / 16; ++q)
+        *(u32x4*)(lds + a + 16 * q) = u32x4{w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]};
+      return;
+    }
+  }
+  if ((a & 3u) == 0u) {
+#pragma unroll
+    for (int q = 0; q < NB / 4; ++q) *(uint32_t*)(lds + a + 4 * q) = w[q];
+  } else if ((a & 1u) == 0u) {
+#pragma unroll
+    for (int q = 0; q < NB / 2; ++q) *(uint16_t*)(lds + a + 2 * q) = (uint16_t)(w[q >> 1] >> (16 * (q & 1)));
+  } else {
+#pragma unroll
+    for (int q = 0; q < NB; ++q) lds[a + q] = (uint8_t)(w[q >> 2] >> (8 * (q & 3)));
+  }
+}
+
+// The canonical planes sit at the same phase (mod 16) as the destination's
+// planes (geometry `cg`), so Phase B moves whole aligned 16-byte chunks.
 template <int ES, int SL>
 __device__ __forceinline__ void relayout_merge(const Side& s, uint32_t nt, const uint8_t* lds, uint8_t* can,
-                                               uint32_t can_stride) {
+                                               const Geo& cg) {
   const uint32_t F = s.ncols / ES;
   const uint32_t quads = (nt + 3u) >> 2;
   const uint32_t items = F * quads;
   for (uint32_t q = threadIdx.x; q < items; q += blockDim.x) {
     const uint32_t f = q / quads;
     const uint32_t r = (q - f * quads) * 4u;
-    uint8_t* out = can + f * can_stride + r * ES;
+    const uint32_t a = f * cg.lds_stride + planar_phase(cg, f) + r * ES;
+    uint32_t out[ES];  // the 4 elements, as ES dwords in memory order
     if constexpr (ES == 2) {
       const uint32_t b0 = read_run4<SL>(s, lds, r, 2 * f), b1 = read_run4<SL>(s, lds, r, 2 * f + 1);
-      u32x2 v = {__builtin_amdgcn_perm(b1, b0, 0x05010400u), __builtin_amdgcn_perm(b1, b0, 0x07030602u)};
-      *(u32x2*)out = v;
+      out[0] = __builtin_amdgcn_perm(b1, b0, 0x05010400u);
+      out[1] = __builtin_amdgcn_perm(b1, b0, 0x07030602u);
     } else {
+      constexpr int DW = ES / 4;
 #pragma unroll
-      for (int h = 0; h < ES / 4; ++h) {  // bytes 4h .. 4h+3 of the elements
+      for (int h = 0; h < DW; ++h) {  // bytes 4h .. 4h+3 of the elements
         uint32_t in[4], o[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) in[k] = read_run4<SL>(s, lds, r, f * ES + 4 * h + k);
         transpose4x4(in, o);
-        if constexpr (ES == 4) {
-          *(u32x4*)out = u32x4{o[0], o[1], o[2], o[3]};
-        } else {  // ES == 8: element j = (dword 0, dword 1)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) *(uint32_t*)(out + 8 * j + 4 * h) = o[j];
-        }
+        for (int j = 0; j < 4; ++j) out[j * DW + h] = o[j];
       }
     }
+    lds_write<4 * ES>(can, a, out);
   }
 }
 
 template <int ES, int SL>
 __device__ __forceinline__ void relayout_split(const Side& s, uint32_t nt, const uint8_t* lds, uint8_t* can,
-                                               uint32_t can_stride) {
+                                               const Geo& cg) {
   const uint32_t F = s.ncols;
   const uint32_t quads = (nt + 3u) >> 2;
   const uint32_t items = F * quads;
@@ -367,10 +410,10 @@ __device__ __forceinline__ void relayout_split(const Side& s, uint32_t nt, const
     const uint32_t r = (q - f * quads) * 4u;
     uint32_t e[ES];
     read_elems4<ES, SL>(s, lds, r, f, e);
-    uint8_t* out = can + (f * ES) * can_stride + r;
+    uint32_t col[ES];  // col[k]: byte k of records r..r+3
     if constexpr (ES == 2) {
-      *(uint32_t*)out = __builtin_amdgcn_perm(e[1], e[0], 0x06040200u);
-      *(uint32_t*)(out + can_stride) = __builtin_amdgcn_perm(e[1], e[0], 0x07050301u);
+      col[0] = __builtin_amdgcn_perm(e[1], e[0], 0x06040200u);
+      col[1] = __builtin_amdgcn_perm(e[1], e[0], 0x07050301u);
     } else {
       constexpr int DW = ES / 4;
 #pragma unroll
@@ -380,8 +423,13 @@ __device__ __forceinline__ void relayout_split(const Side& s, uint32_t nt, const
         for (int j = 0; j < 4; ++j) in[j] = e[j * DW + h];
         transpose4x4(in, o);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) *(uint32_t*)(out + (4 * h + k) * can_stride) = o[k];
+        for (int k = 0; k < 4; ++k) col[4 * h + k] = o[k];
       }
+    }
+#pragma unroll
+    for (int k = 0; k < ES; ++k) {
+      const uint32_t c = f * ES + k;
+      lds_write<4>(can, c * cg.lds_stride + planar_phase(cg, c) + r, &col[k]);
     }
   }
 }
@@ -440,18 +488,161 @@ __device__ __forceinline__ void store_colrun(const G& s, const Side& d, uint64_t
             const uint32_t* p = (const uint32_t*)(lds + a);
             v = u32x4{p[0], p[1], p[2], p[3]};
           } else {
-            uint32_t t[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-            for (uint32_t k = 0; k < 16; ++k) t[k >> 2] |= (uint32_t)lds[a + k] << (8u * (k & 3u));
-            v = u32x4{t[0], t[1], t[2], t[3]};
+            // five aligned dwords and byte funnel shifts; the fifth dword
+            // starts inside the run and ends before the next 4-aligned
+            // plane boundary, so it stays in this plane's allocation
+            const uint32_t* p = (const uint32_t*)(lds + (a & ~3u));
+            const uint32_t sh = a & 3u;
+            const uint32_t d0 = p[0], d1 = p[1], d2 = p[2], d3 = p[3], d4 = p[4];
+            v = u32x4{__builtin_amdgcn_alignbyte(d1, d0, sh), __builtin_amdgcn_alignbyte(d2, d1, sh),
+                      __builtin_amdgcn_alignbyte(d3, d2, sh), __builtin_amdgcn_alignbyte(d4, d3, sh)};
           }
-          __builtin_amdgcn_raw_buffer_store_b128(v, rs, off, 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b128(v, rs, off, 0, kStoreNT);
           return;
         }
       }
     }
     raw_chunk<U, DL, SL>(s, d, nt, lds, rs, seg, off, x0, len);
   });
+}
+
+// ---------------------------------------------------------------------------
+// Fused relayout + store for Bytesplit pairs whose byte runs stay 4-byte
+// aligned.  Work items are (field f, 64 blocks of 4 records); the field is
+// wave-uniform, so every byte column a wave writes has a uniform buffer
+// resource (also for multi-blob destinations).
+//   split: 4 elements of field f (one 4 x ES byte block) are read from the
+//          source tile, transposed, and the ES four-byte words are stored to
+//          the destination byte columns: 256 contiguous bytes per column and
+//          wave instruction.
+//   merge: ES four-byte words (byte k of records r..r+3) are read from the
+//          source byte columns, transposed into 4 elements and stored as one
+//          4*ES-byte run of field f: 1 KiB contiguous per wave instruction.
+// ---------------------------------------------------------------------------
+
+// Column c of a planar or AoSoA side (cs = column size): the byte offset
+// where the tile's run of that column starts (wave-uniform; tiles start on
+// AoSoA block boundaries) and the offset of tile-local record r from there.
+template <int DL>
+__device__ __forceinline__ uint64_t col_base(const Side& d, uint64_t i0, uint32_t c) {
+  if constexpr (DL == LY_PLANAR) return (d.mb ? 0ull : d.n * d.cs * c) + i0 * d.cs;
+  else return i0 * d.rec_bytes + (uint64_t)c * d.lanes * d.cs;
+}
+
+template <int DL>
+__device__ __forceinline__ uint32_t col_local(const Side& d, uint32_t r) {
+  if constexpr (DL == LY_PLANAR) {
+    return r * d.cs;
+  } else {
+    const uint32_t blk = fdiv(r, d.div_L);
+    return blk * d.lanes * d.rec_bytes + (r - blk * d.lanes) * d.cs;
+  }
+}
+
+template <int ES, int SL, int DL>
+__device__ __forceinline__ void store_split_fused(const Side& s, const Side& d, uint64_t i0, uint32_t nt,
+                                                  const uint8_t* lds) {
+  const uint32_t F = s.ncols;
+  const uint32_t quads = (nt + 3u) >> 2;
+  const uint32_t gpf = (quads + 63u) >> 6;  // groups of 64 quads per field
+  const uint32_t items = F * gpf;
+  const uint32_t w0 = wave_id(), nw = num_waves(), lane = lane_id();
+  for (uint32_t it = w0; it < items; it += nw) {
+    const uint32_t f = it / gpf;
+    const uint32_t q = (it - f * gpf) * 64u + lane;
+    if (q >= quads) continue;
+    const uint32_t r = q * 4u;
+    uint32_t e[ES];
+    read_elems4<ES, SL>(s, lds, r, f, e);
+    uint32_t col[ES];  // col[k]: byte k of records r..r+3
+    if constexpr (ES == 2) {
+      col[0] = __builtin_amdgcn_perm(e[1], e[0], 0x06040200u);
+      col[1] = __builtin_amdgcn_perm(e[1], e[0], 0x07050301u);
+    } else {
+      constexpr int DW = ES / 4;
+#pragma unroll
+      for (int h = 0; h < DW; ++h) {
+        uint32_t in[4], o[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) in[j] = e[j * DW + h];
+        transpose4x4(in, o);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) col[4 * h + k] = o[k];
+      }
+    }
+    const uint32_t nrec = nt - r < 4u ? nt - r : 4u;
+#pragma unroll
+    for (int k = 0; k < ES; ++k) {
+      const uint32_t c = f * ES + k;
+      const void* blob = (DL == LY_PLANAR && d.mb) ? d.blob[c] : d.blob[0];
+      // the runs are 4-byte aligned (checked on the host); the resource base
+      // is the run start aligned down to 16 bytes
+      const uint64_t cb = col_base<DL>(d, i0, c);
+      const uint64_t base = cb & ~15ull;
+      const auto rs = make_rsrc((const uint8_t*)blob + base, d.blob_size - base);
+      const uint32_t lo = (uint32_t)(cb - base) + col_local<DL>(d, r);
+      if (nrec == 4u) {
+        __builtin_amdgcn_raw_buffer_store_b32(col[k], rs, lo, 0, 0);
+      } else {
+        for (uint32_t j = 0; j < nrec; ++j)
+          __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(col[k] >> (8u * j)), rs, lo + j, 0, 0);
+      }
+    }
+  }
+}
+
+template <int ES, int SL, int DL>
+__device__ __forceinline__ void store_merge_fused(const Side& s, const Side& d, uint64_t i0, uint32_t nt,
+                                                  const uint8_t* lds) {
+  const uint32_t F = d.ncols;
+  const uint32_t quads = (nt + 3u) >> 2;
+  const uint32_t gpf = (quads + 63u) >> 6;
+  const uint32_t items = F * gpf;
+  const uint32_t w0 = wave_id(), nw = num_waves(), lane = lane_id();
+  for (uint32_t it = w0; it < items; it += nw) {
+    const uint32_t f = it / gpf;
+    const uint32_t q = (it - f * gpf) * 64u + lane;
+    const void* blob = (DL == LY_PLANAR && d.mb) ? d.blob[f] : d.blob[0];
+    const uint64_t cb = col_base<DL>(d, i0, f);
+    const uint64_t base = cb & ~15ull;
+    const auto rs = make_rsrc((const uint8_t*)blob + base, d.blob_size - base);
+    if (q >= quads) continue;
+    const uint32_t r = q * 4u;
+    uint32_t out[ES];  // the 4 elements, as ES dwords
+    if constexpr (ES == 2) {
+      const uint32_t b0 = read_run4<SL>(s, lds, r, 2 * f), b1 = read_run4<SL>(s, lds, r, 2 * f + 1);
+      out[0] = __builtin_amdgcn_perm(b1, b0, 0x05010400u);
+      out[1] = __builtin_amdgcn_perm(b1, b0, 0x07030602u);
+    } else {
+      constexpr int DW = ES / 4;
+#pragma unroll
+      for (int h = 0; h < DW; ++h) {
+        uint32_t in[4], o[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) in[k] = read_run4<SL>(s, lds, r, f * ES + 4 * h + k);
+        transpose4x4(in, o);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) out[j * DW + h] = o[j];
+      }
+    }
+    const uint32_t lo = (uint32_t)(cb - base) + col_local<DL>(d, r);
+    const uint32_t nrec = nt - r < 4u ? nt - r : 4u;
+    if (nrec == 4u) {
+      if constexpr (ES == 2) {
+        __builtin_amdgcn_raw_buffer_store_b64(u32x2{out[0], out[1]}, rs, lo, 0, kStoreNT);
+      } else {
+#pragma unroll
+        for (int q4 = 0; q4 < ES / 4; ++q4)
+          __builtin_amdgcn_raw_buffer_store_b128(u32x4{out[4 * q4], out[4 * q4 + 1], out[4 * q4 + 2], out[4 * q4 + 3]},
+                                                 rs, lo + 16u * q4, 0, kStoreNT);
+      }
+    } else if constexpr (ES == 2) {
+      for (uint32_t j = 0; j < nrec; ++j)
+        __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(out[j >> 1] >> (16u * (j & 1u))), rs, lo + 2u * j, 0, 0);
+    } else {
+      for (uint32_t j = 0; j < nrec * (ES / 4u); ++j) __builtin_amdgcn_raw_buffer_store_b32(out[j], rs, lo + 4u * j, 0, 0);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
