@@ -207,7 +207,9 @@ llama_status llama_batch_launch_per_view(llama_batch* batch, void* stream);
 typedef struct llama_batch_info {
   uint32_t n_views;
   uint32_t tile_records;     /* chosen tile size (0: each view's default tile,
-                                1: the same capped to 16 KiB of LDS)            */
+                                1: the same capped to 16 KiB of LDS, 2: each
+                                view's tile grown to the LDS of the largest
+                                default tile; else records per tile)           */
   uint32_t grid;             /* persistent workgroups                          */
   uint64_t total_tiles;
   uint64_t algorithmic_bytes;/* mapped bytes read + mapped bytes written       */

@@ -59,13 +59,24 @@ llama_status build_items(llama_batch* b, uint32_t T, std::vector<BatchItem>& ite
   std::vector<BatchItem> plans(n);
   std::vector<uint64_t> tiles(n);
   std::vector<uint64_t> key(n);
+  // T = 2: every view's tile grown to the LDS that the largest default tile
+  // needs (one launch allocates that much for every workgroup anyway)
+  uint32_t fill_cap = 0;
+  if (T == 2) {
+    for (size_t v = 0; v < n; ++v) {
+      Plan p;
+      llama_status st = plan_copy(b->srcs[v], b->dsts[v], nullptr, p);
+      if (st != LLAMA_OK) return st;
+      fill_cap = std::max(fill_cap, p.lds);
+    }
+  }
   lds = 0;
   for (size_t v = 0; v < n; ++v) {
     Plan p;
     // T = 0: each view's default tile; T = 1: the same, capped to 16 KiB of
     // LDS so that one kernel keeps full occupancy for every view
-    llama_launch_params lp{T > 1 ? T : 0u, 0};
-    llama_status st = plan_copy(b->srcs[v], b->dsts[v], &lp, p, T == 1 ? 16384u : 0u);
+    llama_launch_params lp{T > 2 ? T : 0u, 0};
+    llama_status st = plan_copy(b->srcs[v], b->dsts[v], &lp, p, T == 1 ? 16384u : fill_cap, T == 2);
     if (st != LLAMA_OK) return st;
     if (p.kind != PK_RAW) return fail(LLAMA_ERR_UNSUPPORTED, "batched copies move physical layouts only");
     plans[v] = BatchItem{};
@@ -232,8 +243,9 @@ llama_status autotune(llama_batch* b, uint64_t granule, uint32_t& bestT, uint32_
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   // tile candidates: 0 (each view's default tile), 1 (default tile capped to
-  // 16 KiB of LDS) and fixed sizes
-  std::vector<uint32_t> tiles = {0u, 1u};
+  // 16 KiB of LDS), 2 (tiles grown to the largest default tile's LDS) and
+  // fixed sizes
+  std::vector<uint32_t> tiles = {0u, 1u, 2u};
   for (uint32_t T : {512u, 1024u})
     if (T % granule == 0) tiles.push_back(T);
   double best = 1e30, best_pv = 1e30;
@@ -241,7 +253,8 @@ llama_status autotune(llama_batch* b, uint64_t granule, uint32_t& bestT, uint32_
   for (uint32_t T : tiles) {
     if (upload(b, T) != LLAMA_OK) continue;  // e.g. a tile that does not fit in LDS
     for (uint32_t mult : {8u, 32u, 128u, 0u}) {  // 0: one workgroup per tile
-      const uint32_t G = (uint32_t)std::min<uint64_t>(mult ? (uint64_t)cus * mult : b->total_tiles, b->total_tiles);
+      const uint32_t G = (uint32_t)std::max<uint64_t>(
+          1, std::min<uint64_t>(mult ? (uint64_t)cus * mult : b->total_tiles, b->total_tiles));
       hipError_t le = hipSuccess;
       auto run = [&]() {
         hipError_t e = launch_batch(b->d_items, b->d_prefix, (uint32_t)b->total_tiles, (uint32_t)b->srcs.size(), G, b->lds, b->cap);
@@ -257,7 +270,7 @@ llama_status autotune(llama_batch* b, uint64_t granule, uint32_t& bestT, uint32_
       }
     }
     std::vector<Plan> pv;
-    if (T == 1 || per_view_plans(b, T, pv) != LLAMA_OK) continue;  // per-view launches need no cap
+    if (T == 1 || T == 2 || per_view_plans(b, T, pv) != LLAMA_OK) continue;  // per-view launches need no cap
     auto run_pv = [&]() {
       for (auto& p : pv) (void)launch_plan(p, b->cap);
     };
@@ -318,8 +331,14 @@ llama_status llama_batch_create(uint32_t n, const llama_view* const* srcs, llama
   b->grid = G;
   b->pv_tile = P;
   (void)hipStreamSynchronize(b->cap);
-  if ((st = upload(b.get(), T)) != LLAMA_OK || (st = per_view_plans(b.get(), P, b->pv)) != LLAMA_OK ||
-      (st = capture(b.get())) != LLAMA_OK) {
+  st = upload(b.get(), T);
+  if (st == LLAMA_OK) st = per_view_plans(b.get(), P, b->pv);
+  if (st == LLAMA_OK) {
+    // a cached grid may exceed this batch's tile count
+    b->grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(b->grid, b->total_tiles));
+    st = capture(b.get());
+  }
+  if (st != LLAMA_OK) {
     release_device(b.get());
     (void)hipStreamDestroy(b->cap);
     return st;

@@ -389,7 +389,7 @@ static Codec codec_of(llama_scalar t) {
 }
 
 llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama_launch_params* p,
-                       Plan& plan, uint32_t lds_cap) {
+                       Plan& plan, uint32_t lds_cap, bool fill) {
   if (!src || !dst) return fail(LLAMA_ERR_INVALID_ARG, "view is NULL");
   if (src->rec != dst->rec) return fail(LLAMA_ERR_RECORD_MISMATCH, "source and destination records differ");
   if (src->n != dst->n) return fail(LLAMA_ERR_RECORD_MISMATCH, "source and destination record counts differ");
@@ -416,16 +416,16 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     plan.kind = PK_RAW;
     plan.unit = S.es;  // leaf bytes
     plan.args.mode = S.cs == D.cs ? RM_DIRECT : (S.cs == 1 ? RM_MERGE : RM_SPLIT);
-    // fused relayout: the destination keeps runs of 4 records per column,
-    // 4-byte aligned (split: byte columns) or aligned to the store width
-    // (merge: element columns)
-    const uint64_t n = src->n;
+    // fused relayout: the destination keeps runs of 4 records per column.
+    // Planar destinations always qualify (the kernels adapt to a plane
+    // start off the dword / 16-byte grid); AoSoA needs runs that stay
+    // aligned to the store width in every block.
     if (plan.args.mode == RM_SPLIT) {
-      const bool ok = (D.layout == LY_PLANAR && (D.mb || n % 4 == 0)) || (D.layout == LY_AOSOA && D.lanes % 4 == 0);
+      const bool ok = D.layout == LY_PLANAR || (D.layout == LY_AOSOA && D.lanes % 4 == 0);
       if (ok) plan.args.mode = RM_SPLIT_FUSED;
     } else if (plan.args.mode == RM_MERGE) {
       const uint64_t A = D.es >= 4 ? 16 : 4 * D.es;  // store width of 4 elements (up to 16 bytes)
-      const bool ok = (D.layout == LY_PLANAR && (D.mb || (n * D.es) % A == 0)) ||
+      const bool ok = D.layout == LY_PLANAR ||
                       (D.layout == LY_AOSOA && D.lanes % 4 == 0 && ((uint64_t)D.lanes * D.rec_bytes) % A == 0 &&
                        ((uint64_t)D.lanes * D.es) % A == 0);
       if (ok) plan.args.mode = RM_MERGE_FUSED;
@@ -472,6 +472,11 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     uint64_t k = per ? (target / per) : 1;
     if (k < 1) k = 1;
     while (lds_cap && k > 1 && lds_total(gran * k) > lds_cap) --k;
+    if (fill && lds_cap) {  // grow the tile to the largest one within the cap
+      while (gran * (k + 1) <= 65536 && lds_total(gran * (k + 1)) <= lds_cap &&
+             gran * (k + 1) * dst_bytes <= 65536)
+        ++k;
+    }
     tile = gran * k;
   }
   if (tile > 65536) return fail(LLAMA_ERR_INVALID_ARG, "tile_records must be <= 65536");

@@ -73,9 +73,10 @@ uint64_t tile_granule(const Side& s, const Side& d);
 uint32_t tile_lds_bytes(const Side& s, uint32_t tile);
 
 // lds_cap (bytes, 0 = none) bounds the LDS of the default tile choice
-// (tile_records == 0): the tile shrinks until it fits.
+// (tile_records == 0): the tile shrinks until it fits; with `fill` it also
+// grows to the largest tile within the cap.
 llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama_launch_params* p,
-                       Plan& plan, uint32_t lds_cap = 0);
+                       Plan& plan, uint32_t lds_cap = 0, bool fill = false);
 llama_status launch_plan(const Plan& plan, hipStream_t st);
 
 Div make_div(uint32_t d);

@@ -550,8 +550,10 @@ __device__ __forceinline__ void store_split_fused(const Side& s, const Side& d, 
   for (uint32_t it = w0; it < items; it += nw) {
     const uint32_t f = it / gpf;
     const uint32_t q = (it - f * gpf) * 64u + lane;
-    if (q >= quads) continue;
-    const uint32_t r = q * 4u;
+    // every lane takes part (the cross-lane shift below reads its neighbour);
+    // lanes past the tile read record 0 and store nothing
+    const bool act = q < quads;
+    const uint32_t r = act ? q * 4u : 0u;
     uint32_t e[ES];
     read_elems4<ES, SL>(s, lds, r, f, e);
     uint32_t col[ES];  // col[k]: byte k of records r..r+3
@@ -570,22 +572,43 @@ __device__ __forceinline__ void store_split_fused(const Side& s, const Side& d, 
         for (int k = 0; k < 4; ++k) col[4 * h + k] = o[k];
       }
     }
-    const uint32_t nrec = nt - r < 4u ? nt - r : 4u;
+    const uint32_t nrec = !act ? 0u : (nt - r < 4u ? nt - r : 4u);
 #pragma unroll
     for (int k = 0; k < ES; ++k) {
       const uint32_t c = f * ES + k;
       const void* blob = (DL == LY_PLANAR && d.mb) ? d.blob[c] : d.blob[0];
-      // the runs are 4-byte aligned (checked on the host); the resource base
-      // is the run start aligned down to 16 bytes
+      // the resource base is the run start aligned down to 16 bytes
       const uint64_t cb = col_base<DL>(d, i0, c);
       const uint64_t base = cb & ~15ull;
       const auto rs = make_rsrc((const uint8_t*)blob + base, d.blob_size - base);
       const uint32_t lo = (uint32_t)(cb - base) + col_local<DL>(d, r);
-      if (nrec == 4u) {
-        __builtin_amdgcn_raw_buffer_store_b32(col[k], rs, lo, 0, 0);
+      const uint32_t ph = (uint32_t)cb & 3u;  // run phase: nonzero only for a single-blob plane
+      if (ph == 0u) {
+        if (nrec == 4u) {
+          __builtin_amdgcn_raw_buffer_store_b32(col[k], rs, lo, 0, 0);
+        } else {
+          for (uint32_t j = 0; j < nrec; ++j)
+            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(col[k] >> (8u * j)), rs, lo + j, 0, 0);
+        }
       } else {
-        for (uint32_t j = 0; j < nrec; ++j)
-          __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(col[k] >> (8u * j)), rs, lo + j, 0, 0);
+        // lane l writes the aligned dword at lo - ph: the last ph bytes of
+        // lane l - 1 and its own first 4 - ph bytes.  Bytes whose dword has
+        // no complete owner (wave edges, the tile's last records) go out
+        // one by one, each by the lane holding it.
+        const uint32_t prev = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((lane ? lane - 1u : 0u) * 4u), (int)col[k]);
+        const uint32_t lead = 4u - ph;  // own bytes in the dword at lo - ph
+        const bool full = lane > 0u && nrec >= lead;
+        const bool next_full = lane < 63u && r + 4u + lead <= nt;
+        if (full) {
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_amdgcn_alignbyte(col[k], prev, lead), rs, lo - ph, 0, 0);
+        } else {
+          for (uint32_t j = 0; j < lead && j < nrec; ++j)
+            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(col[k] >> (8u * j)), rs, lo + j, 0, 0);
+        }
+        if (!next_full) {
+          for (uint32_t j = lead; j < nrec; ++j)
+            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(col[k] >> (8u * j)), rs, lo + j, 0, 0);
+        }
       }
     }
   }
@@ -627,14 +650,34 @@ __device__ __forceinline__ void store_merge_fused(const Side& s, const Side& d, 
     }
     const uint32_t lo = (uint32_t)(cb - base) + col_local<DL>(d, r);
     const uint32_t nrec = nt - r < 4u ? nt - r : 4u;
+    // a single-blob plane may start off the 16-byte grid (wave-uniform
+    // phase): then the widest store its alignment allows
+    const uint32_t ph = (uint32_t)cb & 15u;
     if (nrec == 4u) {
       if constexpr (ES == 2) {
-        __builtin_amdgcn_raw_buffer_store_b64(u32x2{out[0], out[1]}, rs, lo, 0, kStoreNT);
-      } else {
+        if ((ph & 7u) == 0u) {
+          __builtin_amdgcn_raw_buffer_store_b64(u32x2{out[0], out[1]}, rs, lo, 0, kStoreNT);
+        } else if ((ph & 3u) == 0u) {
+          __builtin_amdgcn_raw_buffer_store_b32(out[0], rs, lo, 0, kStoreNT);
+          __builtin_amdgcn_raw_buffer_store_b32(out[1], rs, lo + 4u, 0, kStoreNT);
+        } else {
+#pragma unroll
+          for (uint32_t j = 0; j < 4u; ++j)
+            __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(out[j >> 1] >> (16u * (j & 1u))), rs, lo + 2u * j, 0,
+                                                  kStoreNT);
+        }
+      } else if (ph == 0u) {
 #pragma unroll
         for (int q4 = 0; q4 < ES / 4; ++q4)
           __builtin_amdgcn_raw_buffer_store_b128(u32x4{out[4 * q4], out[4 * q4 + 1], out[4 * q4 + 2], out[4 * q4 + 3]},
                                                  rs, lo + 16u * q4, 0, kStoreNT);
+      } else if ((ph & 7u) == 0u) {
+#pragma unroll
+        for (int q2 = 0; q2 < ES / 2; ++q2)
+          __builtin_amdgcn_raw_buffer_store_b64(u32x2{out[2 * q2], out[2 * q2 + 1]}, rs, lo + 8u * q2, 0, kStoreNT);
+      } else {
+#pragma unroll
+        for (int j = 0; j < ES; ++j) __builtin_amdgcn_raw_buffer_store_b32(out[j], rs, lo + 4u * j, 0, kStoreNT);
       }
     } else if constexpr (ES == 2) {
       for (uint32_t j = 0; j < nrec; ++j)

@@ -45,8 +45,9 @@ def test_batch_graph_replays_match_oracle():
     batch = lm.Batch([v[0] for v in views], [v[1] for v in views])
     info = batch.info()
     say("batch info", info)
-    # tile code: 0 = each view's default tile, 1 = the same capped to 16 KiB of LDS
-    assert info["n_views"] == 120 and (info["tile_records"] in (0, 1) or info["tile_records"] % 128 == 0)
+    # tile code: 0 = each view's default tile, 1 = the same capped to 16 KiB of LDS,
+    # 2 = grown to the largest default tile's LDS; else records per tile
+    assert info["n_views"] == 120 and (info["tile_records"] in (0, 1, 2) or info["tile_records"] % 128 == 0)
     reset(views)
     for rep in range(3):
         batch.launch()
@@ -77,3 +78,30 @@ def test_batch_tune_cache_roundtrip(tmp_path):
     check(views, "cached batch")
     b1.close()
     b2.close()
+
+
+@pytest.mark.parametrize("code,grid", [(0, 256), (1, 2048), (2, 97), (2, 0), (512, 1000)])
+def test_batch_every_tile_choice_matches_oracle(tmp_path, code, grid):
+    """Every tile choice the autotuner can make, forced through the tune cache
+    (the cached entry is used as is), with a persistent grid smaller than, and
+    one workgroup per, tile."""
+    torch = pytest.importorskip("torch")
+    views = make_batch(50, 1, 20000, seed=3)
+    path = tmp_path / "tune.json"
+    b0 = lm.Batch([v[0] for v in views], [v[1] for v in views], tune_cache=str(path))
+    total = b0.info()["total_tiles"]
+    b0.close()
+    text = path.read_text()
+    import re
+    g = grid if grid else 1 << 30  # 0: one workgroup per tile (clamped below)
+    text = re.sub(r'"tile_records": \d+, "grid": \d+', '"tile_records": %d, "grid": %d' % (code, min(g, 1 << 20)), text)
+    path.write_text(text)
+    b = lm.Batch([v[0] for v in views], [v[1] for v in views], tune_cache=str(path))
+    info = b.info()
+    say("forced", code, grid, info, "code-0 tiles", total)
+    assert info["tune_seconds"] == 0 and info["tile_records"] == code
+    reset(views)
+    b.launch()
+    torch.cuda.synchronize()
+    check(views, "tile code %d grid %d" % (code, grid))
+    b.close()

@@ -51,7 +51,7 @@ def test_cfg1_f64_records(n):
 MIXED = [
     {"kind": "aos", "packed": True}, {"kind": "aosoa", "lanes": 3}, {"kind": "aosoa", "lanes": 48},
     {"kind": "aosoa", "lanes": 1}, {"kind": "bytesplit", "inner": {"kind": "aos"}},
-    {"kind": "bytesplit", "inner": {"kind": "soa_mb"}},
+    {"kind": "bytesplit", "inner": {"kind": "soa_mb"}}, {"kind": "bytesplit", "inner": {"kind": "soa_sb"}},
     {"kind": "bytesplit", "inner": {"kind": "aosoa", "lanes": 8}},
     {"kind": "bytesplit", "inner": {"kind": "aosoa", "lanes": 32}},
     {"kind": "soa_sb"}, {"kind": "aos"},
