@@ -450,8 +450,11 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     if (mode == RM_SPLIT) return (uint64_t)F * ES * (t + 16u);
     return 0;
   };
+  // pack: the tile's stream-word image (t * B / 8 bytes per field)
+  const bool pack = plan.kind == PK_PACK;
   auto lds_total = [&](uint64_t t) -> uint64_t {
     const uint64_t a = tile_lds_bytes(S, (uint32_t)t);
+    if (pack) return ((a + 15u) & ~15ull) + (uint64_t)D.ncols * (t * D.bits / 8u);
     return canonical ? ((a + 15u) & ~15ull) + can_bytes(t) : a;
   };
   const uint64_t gran = tile_granule(S, D);
@@ -466,11 +469,19 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     // about 16 KiB per tile image on the larger side (32 KiB with two images).
     // Byte planes (a planar Bytesplit side) need longer tiles to fill whole
     // 1 KiB wave groups: about 28 KiB with one such side, 21 KiB with two.
+    // Pack holds the source tile and its stream-word image in LDS: about
+    // 24 KiB in all.  Unpack writes its (larger) output from registers, so
+    // only its stream tile counts: about 16 KiB, up to a 64 KiB output tile.
     const bool bs = S.layout == LY_PLANAR && S.cs == 1, bd = D.layout == LY_PLANAR && D.cs == 1;
-    const uint64_t target = canonical ? 32768 : (bs && bd) ? 21504 : (bs || bd) ? 28672 : 16384;
-    uint64_t per = std::max<uint64_t>(lds_total(gran), gran * dst_bytes);
+    const uint64_t target = pack ? 24576
+                            : canonical ? 32768
+                            : (bs && bd) ? 21504
+                            : (bs || bd) ? 28672
+                                         : 16384;
+    uint64_t per = plan.kind == PK_UNPACK ? lds_total(gran) : std::max<uint64_t>(lds_total(gran), gran * dst_bytes);
     uint64_t k = per ? (target / per) : 1;
     if (k < 1) k = 1;
+    while (k > 1 && (gran * k > 65536 || gran * k * dst_bytes > 65536)) --k;
     while (lds_cap && k > 1 && lds_total(gran * k) > lds_cap) --k;
     if (fill && lds_cap) {  // grow the tile to the largest one within the cap
       while (gran * (k + 1) <= 65536 && lds_total(gran * (k + 1)) <= lds_cap &&
@@ -517,6 +528,7 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
       plan.args.can_off = (uint32_t)((tile_lds_bytes(S, (uint32_t)tile) + 15u) & ~15u);
     }
   }
+  if (pack) plan.args.can_off = (uint32_t)((tile_lds_bytes(S, (uint32_t)tile) + 15u) & ~15u);
   plan.args.tile = (uint32_t)tile;
   plan.ntiles = (src->n + tile - 1) / tile;
   if (plan.ntiles > 0xFFFFFFFFull) return fail(LLAMA_ERR_INDEX_OVERFLOW, "too many tiles");

@@ -127,11 +127,11 @@ __device__ __forceinline__ void phase_b_conv(const Side& s, const Side& d, uint6
 
 template <int CODEC>
 __device__ __forceinline__ void phase_b_pack(const Side& s, const Side& d, uint64_t i0, uint32_t nt,
-                                             const uint8_t* lds) {
+                                             const uint8_t* lds, uint32_t* words, uint32_t wstride) {
   switch (s.layout) {
-    case LY_AOS: store_pack<CODEC, LY_AOS>(s, d, i0, nt, lds); break;
-    case LY_PLANAR: store_pack<CODEC, LY_PLANAR>(s, d, i0, nt, lds); break;
-    default: store_pack<CODEC, LY_AOSOA>(s, d, i0, nt, lds); break;
+    case LY_AOS: store_pack<CODEC, LY_AOS>(s, d, i0, nt, lds, words, wstride); break;
+    case LY_PLANAR: store_pack<CODEC, LY_PLANAR>(s, d, i0, nt, lds, words, wstride); break;
+    default: store_pack<CODEC, LY_AOSOA>(s, d, i0, nt, lds, words, wstride); break;
   }
 }
 
@@ -167,10 +167,15 @@ __global__ __launch_bounds__(kThreads) void k_tile(const TileArgs a) {
     const uint64_t i0 = (uint64_t)t * a.tile;
     const uint64_t left = a.src.n - i0;
     const uint32_t nt = left < (uint64_t)a.tile ? (uint32_t)left : a.tile;
+    // pack: the stream-word image of the tile (one plane of tile * B / 32
+    // words per field) follows the source image in LDS
+    uint32_t* words = (uint32_t*)(lds + a.can_off);
+    const uint32_t wstride = (a.tile * a.dst.bits) >> 5;
+    if constexpr (KIND == 2) pack_clear_words(words, a.dst.ncols * wstride);
     load_tile(a.src, i0, nt, lds);
     wait_tile_loads();
     if constexpr (KIND == 1) phase_b_conv<P0, U>(a.src, a.dst, i0, nt, lds);
-    else if constexpr (KIND == 2) phase_b_pack<P0>(a.src, a.dst, i0, nt, lds);
+    else if constexpr (KIND == 2) phase_b_pack<P0>(a.src, a.dst, i0, nt, lds, words, wstride);
     else phase_b_unpack<P0, U>(a.src, a.dst, i0, nt, lds);
     __syncthreads();
   }

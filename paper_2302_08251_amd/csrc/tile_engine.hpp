@@ -726,17 +726,23 @@ __device__ __forceinline__ uint64_t cvt_f32_f64(uint32_t x) {
 __device__ __forceinline__ uint32_t enc_f32(uint32_t x, uint32_t E, uint32_t M) {
   const uint32_t sh = 23u - M;
   const uint32_t bias = (1u << (E - 1u)) - 1u;
-  const uint32_t emin = 128u - bias;   // smallest source exponent field with a target normal
-  const uint32_t emaxf = 127u + bias;  // largest source exponent field that stays finite
+  const uint32_t emin = 128u - bias;  // smallest source exponent field with a target normal
   const uint32_t inf_code = ((1u << E) - 1u) << M;
-  const uint32_t ax = x & 0x7FFFFFFFu, e = ax >> 23, m = ax & 0x7FFFFFu;
-  const uint32_t c_norm = ((e - emin + 1u) << M) | (m >> sh);
-  const uint32_t sig = e ? (m | 0x800000u) : m;
-  const uint32_t dsh = emin - (e ? e : 1u) + sh;
+  const uint32_t ax = x & 0x7FFFFFFFu;
+  const uint32_t t = ax >> sh;  // (exponent field << M) | truncated mantissa
+  // target normal: rebias the exponent field.  A finite value past the
+  // target range lands at or above the Inf code, so the min maps it to Inf.
+  const uint32_t c_norm = min(t - ((emin - 1u) << M), inf_code);
+  // target subnormal: the significand shifted down, truncated
+  const uint32_t e = ax >> 23;
+  const uint32_t sig = (ax & 0x7FFFFFu) | (e ? 0x800000u : 0u);
+  const uint32_t dsh = emin + sh - max(e, 1u);
   const uint32_t c_sub = dsh < 32u ? (sig >> dsh) : 0u;
+  // NaN: quiet, keeping the top mantissa bits (with M = 0 it becomes Inf)
   const uint32_t quiet = M ? (1u << (M - 1u)) : 0u;
-  const uint32_t c_inf = inf_code | ((ax > 0x7F800000u && M) ? ((m >> sh) | quiet) : 0u);
-  const uint32_t c = e > emaxf ? c_inf : (e >= emin ? c_norm : c_sub);
+  const uint32_t c_nan = inf_code | quiet | (t & ((1u << M) - 1u));
+  uint32_t c = ax >= (emin << 23) ? c_norm : c_sub;
+  c = ax > 0x7F800000u ? c_nan : c;
   return c | ((x >> 31) << (E + M));
 }
 
@@ -744,21 +750,19 @@ __device__ __forceinline__ uint32_t dec_f32(uint32_t c, uint32_t E, uint32_t M) 
   const uint32_t sh = 23u - M;
   const uint32_t bias = (1u << (E - 1u)) - 1u;
   const uint32_t emax = (1u << E) - 1u;
-  const uint32_t e = (c >> M) & emax, m = c & ((1u << M) - 1u);
-  const uint32_t sign = ((c >> (E + M)) & 1u) << 31;
-  uint32_t r;
-  if (e == emax) {
-    r = 0x7F800000u | (m << sh);
-  } else if (e) {
-    r = ((e + 127u - bias) << 23) | (m << sh);
-  } else if (m == 0u) {
-    r = 0u;
-  } else {  // target subnormal m * 2^(1 - bias - M)
-    const int p = 31 - __builtin_clz(m);
-    const int u = 1 - (int)bias - (int)M + p;
-    r = u >= -126 ? (((uint32_t)(u + 127) << 23) | ((m ^ (1u << p)) << (23 - p))) : (m << sh);
-  }
-  return r | sign;
+  const uint32_t cm = c & ((1u << (E + M)) - 1u);  // code without its sign
+  // normal, Inf and NaN codes: exponent and mantissa fields move up as one;
+  // the exponent field is then rebiased (Inf / NaN: to all ones)
+  const uint32_t up = cm >= (emax << M) ? (255u - emax) << 23 : (127u - bias) << 23;
+  const uint32_t r_norm = (cm << sh) + up;
+  // subnormal codes (and zero): m * 2^(1 - bias - M), exact in float32
+  // (an integer below 2^23 times a power of two)
+  const int ex = 1 - (int)bias - (int)M;  // >= -149
+  const float p2 = ex >= -126 ? __builtin_bit_cast(float, (uint32_t)(ex + 127) << 23)
+                              : __builtin_bit_cast(float, 1u << (ex + 149));
+  const uint32_t r_sub = __builtin_bit_cast(uint32_t, (float)cm * p2);
+  const uint32_t r = cm < (1u << M) ? r_sub : r_norm;
+  return r | ((c >> (E + M)) << 31);
 }
 
 __device__ __forceinline__ uint32_t enc_f64(uint64_t x, uint32_t E, uint32_t M) {
@@ -887,45 +891,49 @@ __device__ __forceinline__ void store_conv(const Side& s, const Side& d, uint64_
 }
 
 // ---------------------------------------------------------------------------
-// Phase B, pack into bit streams.  A wave owns 256 consecutive words of one
-// field's stream; lane l assembles words l, l+64, l+128, l+192 from the codes
-// of the values whose bits they hold.  Neighbouring lanes thus read
-// neighbouring values from LDS (no bank conflicts for any code width) and
-// every store instruction writes 256 contiguous bytes.  Each lane owns whole
-// words, so no two lanes write the same word.
+// Phase B, pack into bit streams (Sec. 3 bit-packed SoA).  Every value of the
+// tile is encoded exactly once and its code ORed into an LDS image of the
+// tile's stream words with LDS atomics (a code spans at most two words).
+// The image starts zeroed, so the bits past the last value stay zero, and
+// goes out with 16-byte stores: a wave writes 1 KiB contiguous per store.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void pack_clear_words(uint32_t* words, uint32_t nwords) {
+  for (uint32_t k = threadIdx.x * 4u; k < nwords; k += blockDim.x * 4u) *(u32x4*)(words + k) = u32x4{0u, 0u, 0u, 0u};
+}
 
 template <int CODEC, int SL>
 __device__ __forceinline__ void store_pack(const Side& s, const Side& d, uint64_t i0, uint32_t nt,
-                                           const uint8_t* lds) {
+                                           const uint8_t* lds, uint32_t* words, uint32_t wstride) {
   constexpr int ES = CodecInfo<CODEC>::ES;
   const uint32_t B = d.bits;
-  const SegGeo g = seg_geo(d, nt);
-  const uint32_t words = g.len >> 2;
-  const uint32_t gps = (words + 255u) >> 8;
-  const uint32_t items = g.nseg * gps;
-  const uint32_t w0 = wave_id(), nw = num_waves(), lane = lane_id();
-  for (uint32_t it = w0; it < items; it += nw) {
-    const uint32_t f = it / gps;
-    const uint32_t grp = it - f * gps;
-    const uint64_t start = seg_start(d, f, i0);  // 16-byte aligned: tiles are multiples of 128 records
+  const uint32_t F = d.ncols;
+  for (uint32_t f = 0; f < F; ++f) {
+    uint32_t* wf = words + f * wstride;
+    for (uint32_t r = threadIdx.x; r < nt; r += blockDim.x) {
+      const uint32_t code = encode<CODEC>(fetch_elem<ES, SL>(s, lds, r, f), d);
+      const uint32_t bit = r * B, w = bit >> 5, sh = bit & 31u;
+      __hip_atomic_fetch_or(wf + w, code << sh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (sh + B > 32u)
+        __hip_atomic_fetch_or(wf + w + 1u, code >> (32u - sh), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+  }
+  __syncthreads();
+  const uint32_t nw = (nt * B + 31u) >> 5;  // stream words of this tile
+  const uint32_t nch = (nw + 3u) >> 2;
+  for (uint32_t f = 0; f < F; ++f) {
+    // tiles are multiples of 128 records, so every tile's stream starts 16-byte aligned
+    const uint64_t start = seg_start(d, f, i0);
     const auto rs = make_rsrc((const uint8_t*)seg_blob(d, f) + start, d.blob_size - start);
-#pragma unroll
-    for (uint32_t q = 0; q < 4; ++q) {
-      const uint32_t wi = grp * 256u + q * 64u + lane;  // tile-local word index
-      if (wi >= words) continue;
-      const uint32_t bit0 = wi * 32u;
-      uint32_t r = fdiv(bit0, d.div_B);
-      const uint32_t first = bit0 - r * B;
-      uint32_t acc = encode<CODEC>(fetch_elem<ES, SL>(s, lds, r, f), d) >> first;
-      uint32_t nb = B - first;
-      ++r;
-      while (nb < 32u && r < nt) {
-        acc |= encode<CODEC>(fetch_elem<ES, SL>(s, lds, r, f), d) << nb;
-        nb += B;
-        ++r;
+    const uint32_t* wf = words + f * wstride;
+    for (uint32_t c = threadIdx.x; c < nch; c += blockDim.x) {
+      const u32x4 v = *(const u32x4*)(wf + 4u * c);
+      if (4u * c + 4u <= nw) {
+        __builtin_amdgcn_raw_buffer_store_b128(v, rs, 16u * c, 0, kStoreNT);
+      } else {
+        __builtin_amdgcn_raw_buffer_store_b32(v[0], rs, 16u * c, 0, 0);
+        if (4u * c + 1u < nw) __builtin_amdgcn_raw_buffer_store_b32(v[1], rs, 16u * c + 4u, 0, 0);
+        if (4u * c + 2u < nw) __builtin_amdgcn_raw_buffer_store_b32(v[2], rs, 16u * c + 8u, 0, 0);
       }
-      __builtin_amdgcn_raw_buffer_store_b32(acc, rs, wi * 4u, 0, 0);
     }
   }
 }
