@@ -901,6 +901,15 @@ __device__ __forceinline__ void pack_clear_words(uint32_t* words, uint32_t nword
   for (uint32_t k = threadIdx.x * 4u; k < nwords; k += blockDim.x * 4u) *(u32x4*)(words + k) = u32x4{0u, 0u, 0u, 0u};
 }
 
+// ORs the W-bit group `code` into the word image at stream bit `bit` (it
+// spans at most two words).
+__device__ __forceinline__ void or_bits(uint32_t* wf, uint32_t bit, uint32_t code, uint32_t W) {
+  const uint32_t w = bit >> 5, sh = bit & 31u;
+  __hip_atomic_fetch_or(wf + w, code << sh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  if (sh + W > 32u)
+    __hip_atomic_fetch_or(wf + w + 1u, code >> (32u - sh), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 template <int CODEC, int SL>
 __device__ __forceinline__ void store_pack(const Side& s, const Side& d, uint64_t i0, uint32_t nt,
                                            const uint8_t* lds, uint32_t* words, uint32_t wstride) {
@@ -909,13 +918,35 @@ __device__ __forceinline__ void store_pack(const Side& s, const Side& d, uint64_
   const uint32_t F = d.ncols;
   for (uint32_t f = 0; f < F; ++f) {
     uint32_t* wf = words + f * wstride;
-    for (uint32_t r = threadIdx.x; r < nt; r += blockDim.x) {
-      const uint32_t code = encode<CODEC>(fetch_elem<ES, SL>(s, lds, r, f), d);
-      const uint32_t bit = r * B, w = bit >> 5, sh = bit & 31u;
-      __hip_atomic_fetch_or(wf + w, code << sh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      if (sh + B > 32u)
-        __hip_atomic_fetch_or(wf + w + 1u, code >> (32u - sh), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if constexpr (SL == LY_PLANAR && ES == 4) {
+      if (s.cs == 4u && (planar_phase(s, f) & 15u) == 0u) {  // element planes (not Bytesplit byte planes)
+        // four consecutive values per lane from one 16-byte LDS read; their
+        // codes go in as one group (B <= 8), two pairs (B <= 16) or singly,
+        // which cuts the atomics and the lanes that meet on one word
+        const uint8_t* plane = lds + f * s.lds_stride;
+        const uint32_t quads = (nt + 3u) >> 2;
+        for (uint32_t q = threadIdx.x; q < quads; q += blockDim.x) {
+          const u32x4 v = *(const u32x4*)(plane + 16u * q);
+          const uint32_t r = 4u * q;
+          uint32_t c[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) c[k] = r + k < nt ? encode<CODEC>(v[k], d) : 0u;
+          const uint32_t bit = r * B;
+          if (B <= 8u) {
+            or_bits(wf, bit, c[0] | (c[1] << B) | (c[2] << (2u * B)) | (c[3] << (3u * B)), 4u * B);
+          } else if (B <= 16u) {
+            or_bits(wf, bit, c[0] | (c[1] << B), 2u * B);
+            or_bits(wf, bit + 2u * B, c[2] | (c[3] << B), 2u * B);
+          } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) or_bits(wf, bit + k * B, c[k], B);
+          }
+        }
+        continue;
+      }
     }
+    for (uint32_t r = threadIdx.x; r < nt; r += blockDim.x)
+      or_bits(wf, r * B, encode<CODEC>(fetch_elem<ES, SL>(s, lds, r, f), d), B);
   }
   __syncthreads();
   const uint32_t nw = (nt * B + 31u) >> 5;  // stream words of this tile

@@ -62,7 +62,7 @@ def test_bitpack_int_all_widths_i32_u32(n):
         rec = [t, t]
         planes = bits_planes(n, rec, seed=n)
         for B in range(1, 33):
-            for phys in (PHYS[0], PHYS[1], PHYS[4]):
+            for phys in (PHYS[0], PHYS[1], PHYS[2], PHYS[4]):
                 say("int", t, B, phys, n)
                 pack_unpack(rec, phys, {"kind": "bitpack_int", "bits": B}, n, planes)
 
@@ -85,13 +85,13 @@ def special_f32_planes(n, nf, seed):
 
 @pytest.mark.parametrize("E", list(range(2, 9)))
 def test_bitpack_float_every_split_f32(E):
-    n = 300
     rec = ["f32"] * 2
-    planes = special_f32_planes(n, 2, seed=E)
-    # include values around each format's range limits
-    for M in range(0, 24):
-        say("float", E, M)
-        pack_unpack(rec, PHYS[0], {"kind": "bitpack_float", "exp": E, "man": M}, n, planes)
+    # AoS, and planar sources whose planes start on and off the 16-byte grid
+    for n, phys in ((300, PHYS[0]), (300, PHYS[1]), (301, PHYS[2])):
+        planes = special_f32_planes(n, 2, seed=E)
+        for M in range(0, 24):
+            say("float", E, M, phys, n)
+            pack_unpack(rec, phys, {"kind": "bitpack_float", "exp": E, "man": M}, n, planes)
 
 
 @pytest.mark.parametrize("E,M", [(8, 15), (11, 20), (5, 10), (8, 7), (11, 0), (2, 29), (9, 22)])
