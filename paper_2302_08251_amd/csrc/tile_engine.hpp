@@ -733,11 +733,15 @@ __device__ __forceinline__ uint32_t enc_f32(uint32_t x, uint32_t E, uint32_t M) 
   // target normal: rebias the exponent field.  A finite value past the
   // target range lands at or above the Inf code, so the min maps it to Inf.
   const uint32_t c_norm = min(t - ((emin - 1u) << M), inf_code);
-  // target subnormal: the significand shifted down, truncated
-  const uint32_t e = ax >> 23;
-  const uint32_t sig = (ax & 0x7FFFFFu) | (e ? 0x800000u : 0u);
-  const uint32_t dsh = emin + sh - max(e, 1u);
-  const uint32_t c_sub = dsh < 32u ? (sig >> dsh) : 0u;
+  // target subnormal: |x| in units of the smallest target subnormal,
+  // 2^(1 - bias - M), truncated.  Scaling by powers of two is exact here
+  // (two factors keep each one finite) and the float-to-integer conversion
+  // truncates.
+  const uint32_t k = bias + M - 1u;  // 0 .. 149
+  const uint32_t k1 = k < 127u ? k : 127u;
+  const float s1 = __builtin_bit_cast(float, (k1 + 127u) << 23), s2 = __builtin_bit_cast(float, (k - k1 + 127u) << 23);
+  const float mag = __builtin_bit_cast(float, ax) * s1 * s2;
+  const uint32_t c_sub = ax < (emin << 23) ? (uint32_t)mag : 0u;
   // NaN: quiet, keeping the top mantissa bits (with M = 0 it becomes Inf)
   const uint32_t quiet = M ? (1u << (M - 1u)) : 0u;
   const uint32_t c_nan = inf_code | quiet | (t & ((1u << M) - 1u));
