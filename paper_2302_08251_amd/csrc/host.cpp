@@ -468,15 +468,15 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
   } else {
     // about 16 KiB per tile image on the larger side (32 KiB with two images).
     // Byte planes (a planar Bytesplit side) need longer tiles to fill whole
-    // 1 KiB wave groups: about 28 KiB with one such side, 21 KiB with two.
+    // 1 KiB wave groups: about 30 KiB with one such side, 24 KiB with two.
     // Pack holds the source tile and its stream-word image in LDS: about
     // 24 KiB in all.  Unpack writes its (larger) output from registers, so
     // only its stream tile counts: about 16 KiB, up to a 64 KiB output tile.
     const bool bs = S.layout == LY_PLANAR && S.cs == 1, bd = D.layout == LY_PLANAR && D.cs == 1;
     const uint64_t target = pack ? 24576
                             : canonical ? 32768
-                            : (bs && bd) ? 21504
-                            : (bs || bd) ? 28672
+                            : (bs && bd) ? 24576
+                            : (bs || bd) ? 30720
                                          : 16384;
     uint64_t per = plan.kind == PK_UNPACK ? lds_total(gran) : std::max<uint64_t>(lds_total(gran), gran * dst_bytes);
     uint64_t k = per ? (target / per) : 1;
@@ -511,6 +511,17 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     std::memset(&g, 0, sizeof(g));
     if (mode == RM_DIRECT) {
       plan.args.colrun = (runs(D) && runs(S)) || (D.layout == LY_AOS && S.layout == LY_AOS);
+    } else if (canonical && mode == RM_MERGE && D.layout == LY_AOS) {
+      // merged straight into the destination's AoS record image
+      plan.args.colrun = 1;
+      g.layout = LY_AOS;
+      g.cs = ES;
+      g.log2cs = log2u(ES);
+      g.ncols = F;
+      g.rec_bytes = F * ES;
+      g.lanes = 1;
+      g.div_L = make_div(F);  // the relayout's (quad, field) split
+      plan.args.can_off = (uint32_t)((tile_lds_bytes(S, (uint32_t)tile) + 15u) & ~15u);
     } else if (canonical) {
       plan.args.colrun = runs(D);
       g.layout = LY_PLANAR;

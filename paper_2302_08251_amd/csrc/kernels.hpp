@@ -36,7 +36,7 @@ template <int U, int DL, int COLRUN, typename G>
 __device__ __forceinline__ void phase_b_dl(const G& s, const Side& d, uint64_t i0, uint32_t nt, const uint8_t* lds) {
   if constexpr (COLRUN) {
     if constexpr (DL == LY_AOS) {
-      store_colrun<U, LY_AOS, LY_AOS>(s, d, i0, nt, lds);  // same record: identical byte images
+      store_identity<U>(s, d, i0, nt, lds);  // AoS image of the same record: identical bytes
     } else {
       if (s.layout == LY_AOSOA) store_colrun<U, DL, LY_AOSOA>(s, d, i0, nt, lds);
       else store_colrun<U, DL, LY_PLANAR>(s, d, i0, nt, lds);
@@ -68,7 +68,10 @@ __device__ __forceinline__ void tile_raw(const TileArgs& a, uint64_t i0, uint32_
     else store_merge_fused<ES, LY_PLANAR, DL>(a.src, a.dst, i0, nt, lds);
   } else if constexpr (RV == RV_MERGE || RV == RV_SPLIT) {
     uint8_t* can = lds + a.can_off;
-    if constexpr (RV == RV_MERGE) {
+    if constexpr (RV == RV_MERGE && DL == LY_AOS) {
+      if (a.src.layout == LY_AOSOA) relayout_merge_aos<ES, LY_AOSOA>(a.src, nt, lds, can, a.can);
+      else relayout_merge_aos<ES, LY_PLANAR>(a.src, nt, lds, can, a.can);
+    } else if constexpr (RV == RV_MERGE) {
       if (a.src.layout == LY_AOSOA) relayout_merge<ES, LY_AOSOA>(a.src, nt, lds, can, a.can);
       else relayout_merge<ES, LY_PLANAR>(a.src, nt, lds, can, a.can);
     } else {

@@ -441,6 +441,48 @@ __device__ __forceinline__ void relayout_split(const Side& s, uint32_t nt, const
 // LDS read and one 128-bit store.  Other chunks take the unit-by-unit path.
 // ---------------------------------------------------------------------------
 
+// MERGE into an AoS destination: the elements go straight into the
+// destination's own record image (record r at r * S, field f at f * ES), so
+// Phase B is a plain 16-byte copy of that image.  Work items are (quad of
+// records, field) with the field fastest: the four element writes of a wave
+// then land on neighbouring words.
+template <int ES, int SL>
+__device__ __forceinline__ void relayout_merge_aos(const Side& s, uint32_t nt, const uint8_t* lds, uint8_t* can,
+                                                   const Geo& cg) {
+  const uint32_t F = cg.ncols;
+  const uint32_t items = ((nt + 3u) >> 2) * F;
+  for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
+    const uint32_t q = fdiv(it, cg.div_L);  // div_L holds the field count here
+    const uint32_t f = it - q * F;
+    const uint32_t r = 4u * q;
+    uint32_t out[ES];  // the 4 elements, as ES dwords in memory order
+    if constexpr (ES == 2) {
+      const uint32_t b0 = read_run4<SL>(s, lds, r, 2 * f), b1 = read_run4<SL>(s, lds, r, 2 * f + 1);
+      out[0] = __builtin_amdgcn_perm(b1, b0, 0x05010400u);
+      out[1] = __builtin_amdgcn_perm(b1, b0, 0x07030602u);
+    } else {
+      constexpr int DW = ES / 4;
+#pragma unroll
+      for (int h = 0; h < DW; ++h) {
+        uint32_t in[4], o[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) in[k] = read_run4<SL>(s, lds, r, f * ES + 4 * h + k);
+        transpose4x4(in, o);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) out[j * DW + h] = o[j];
+      }
+    }
+    uint8_t* base = can + r * cg.rec_bytes + f * ES;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      uint8_t* e = base + j * cg.rec_bytes;
+      if constexpr (ES == 2) *(uint16_t*)e = (uint16_t)(out[j >> 1] >> (16 * (j & 1)));
+      else if constexpr (ES == 4) *(uint32_t*)e = out[j];
+      else *(u32x2*)e = u32x2{out[2 * j], out[2 * j + 1]};
+    }
+  }
+}
+
 template <int U, int DL, int SL, typename G>
 __device__ __forceinline__ void raw_chunk(const G& s, const Side& d, uint32_t nt, const uint8_t* lds,
                                           __amdgpu_buffer_rsrc_t rs, uint32_t seg, uint32_t off, int x0,
@@ -503,6 +545,18 @@ __device__ __forceinline__ void store_colrun(const G& s, const Side& d, uint64_t
       }
     }
     raw_chunk<U, DL, SL>(s, d, nt, lds, rs, seg, off, x0, len);
+  });
+}
+
+// AoS image -> AoS destination of the same record: the LDS image and the
+// destination segment hold the same bytes in the same order (tiles start on
+// 16-byte boundaries), so whole chunks move as they are.
+template <int U, typename G>
+__device__ __forceinline__ void store_identity(const G& s, const Side& d, uint64_t i0, uint32_t nt,
+                                               const uint8_t* lds) {
+  for_dst_chunks(d, i0, nt, [&](__amdgpu_buffer_rsrc_t rs, uint32_t seg, uint32_t off, int x0, uint32_t len) {
+    if (x0 + 16 <= (int)len) __builtin_amdgcn_raw_buffer_store_b128(*(const u32x4*)(lds + x0), rs, off, 0, kStoreNT);
+    else raw_chunk<U, LY_AOS, LY_AOS>(s, d, nt, lds, rs, seg, off, x0, len);
   });
 }
 
