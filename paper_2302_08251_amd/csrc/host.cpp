@@ -473,7 +473,11 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     // 24 KiB in all.  Unpack writes its (larger) output from registers, so
     // only its stream tile counts: about 16 KiB, up to a 64 KiB output tile.
     const bool bs = S.layout == LY_PLANAR && S.cs == 1, bd = D.layout == LY_PLANAR && D.cs == 1;
+    // AoS to AoS (a straight 16-byte copy through LDS) is fastest with short
+    // tiles: about 7 KiB.
+    const bool aos2aos = plan.kind == PK_RAW && mode == RM_DIRECT && S.layout == LY_AOS && D.layout == LY_AOS;
     const uint64_t target = pack ? 24576
+                            : aos2aos ? 7168
                             : canonical ? 32768
                             : (bs && bd) ? 24576
                             : (bs || bd) ? 30720
