@@ -477,6 +477,7 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     // tiles: about 7 KiB.
     const bool aos2aos = plan.kind == PK_RAW && mode == RM_DIRECT && S.layout == LY_AOS && D.layout == LY_AOS;
     const uint64_t target = pack ? 24576
+                            : plan.kind == PK_CONV ? 32768  // ChangeType: 32 KiB on the wider side
                             : aos2aos ? 7168
                             : canonical ? 32768
                             : (bs && bd) ? 24576
