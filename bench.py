@@ -151,6 +151,7 @@ def bench_cfg2(lm, torch, steps, warmup, n):
     off = [pair_gbs[f"{a}->{b}"] for a, b in OFFDIAG]
     return {
         "records": n, "alg_bytes_per_pair": alg, "step_ms": step_med, "step_wall_ms": wall_ms,
+        "step_ms_min": float(np.min(step_ms)), "step_ms_max": float(np.max(step_ms)), "timed_steps": len(step_ms),
         "gbs_step": 36 * alg / (step_med * 1e-3) / 1e9,
         "pair_gbs": {k: round(v, 1) for k, v in pair_gbs.items()},
         "pair_ms": {k: round(v, 4) for k, v in med.items()},
@@ -265,6 +266,8 @@ def bench_cfg4(lm, torch, reps, count):
     alg = info["algorithmic_bytes"]
     res = {"views": count, "records": int(ns.sum()), "alg_bytes": alg,
            "batched_ms": float(np.median(tb)), "per_view_ms": float(np.median(tv)),
+           "batched_ms_min_max": [float(np.min(tb)), float(np.max(tb))],
+           "per_view_ms_min_max": [float(np.min(tv)), float(np.max(tv))],
            "batched_gbs": alg / np.median(tb) / 1e6, "per_view_gbs": alg / np.median(tv) / 1e6,
            "speedup": float(np.median(tv) / np.median(tb)), "tile_records": info["tile_records"],
            "grid": info["grid"], "tune_seconds": info["tune_seconds"], "create_seconds": create_s}
@@ -344,8 +347,8 @@ def cpu_baseline(n_sample):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--records", type=int, default=64 << 20)
     ap.add_argument("--rows", default="cfg3,cfg4,cfg5", help="extra rows to measure (comma list or 'none')")
     ap.add_argument("--cpu-sample", type=int, default=4 << 20)
