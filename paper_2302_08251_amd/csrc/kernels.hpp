@@ -58,10 +58,18 @@ __device__ __forceinline__ void tile_raw(const TileArgs& a, uint64_t i0, uint32_
   load_tile(a.src, i0, nt, lds);
   wait_tile_loads();
   if constexpr (RV == RV_SPLIT_FUSED) {
-    switch (a.src.layout) {
-      case LY_PLANAR: store_split_fused<ES, LY_PLANAR, DL>(a.src, a.dst, i0, nt, lds); break;
-      case LY_AOSOA: store_split_fused<ES, LY_AOSOA, DL>(a.src, a.dst, i0, nt, lds); break;
-      default: store_split_fused<ES, LY_AOS, DL>(a.src, a.dst, i0, nt, lds); break;
+    if (DL == LY_AOSOA && (a.dst.lanes & 15u)) {  // runs of 4 records only
+      switch (a.src.layout) {
+        case LY_PLANAR: store_split_fused<ES, LY_PLANAR, DL>(a.src, a.dst, i0, nt, lds); break;
+        case LY_AOSOA: store_split_fused<ES, LY_AOSOA, DL>(a.src, a.dst, i0, nt, lds); break;
+        default: store_split_fused<ES, LY_AOS, DL>(a.src, a.dst, i0, nt, lds); break;
+      }
+    } else {
+      switch (a.src.layout) {
+        case LY_PLANAR: store_split_fused16<ES, LY_PLANAR, DL>(a.src, a.dst, i0, nt, lds); break;
+        case LY_AOSOA: store_split_fused16<ES, LY_AOSOA, DL>(a.src, a.dst, i0, nt, lds); break;
+        default: store_split_fused16<ES, LY_AOS, DL>(a.src, a.dst, i0, nt, lds); break;
+      }
     }
   } else if constexpr (RV == RV_MERGE_FUSED) {
     if (a.src.layout == LY_AOSOA) store_merge_fused<ES, LY_AOSOA, DL>(a.src, a.dst, i0, nt, lds);

@@ -598,16 +598,27 @@ __device__ __forceinline__ void store_split_fused(const Side& s, const Side& d, 
                                                   const uint8_t* lds) {
   const uint32_t F = s.ncols;
   const uint32_t quads = (nt + 3u) >> 2;
-  const uint32_t gpf = (quads + 63u) >> 6;  // groups of 64 quads per field
+  // Single-blob byte planes start at c * n: with n % 4 != 0 a plane's runs
+  // sit off the dword grid by ph = (c * n) % 4 bytes.  Lane l then writes
+  // the aligned dword made of the last ph bytes of quad q - 1 (its left
+  // neighbour's, via ds_bpermute) and its own first 4 - ph bytes.  So that
+  // every such dword has a complete owner, a wave covers 63 writer quads and
+  // lane 0 recomputes the quad just before them as a helper; only the
+  // tile's first and last quads write single bytes.
+  const bool shifted = DL == LY_PLANAR && !d.mb && (d.n & 3u);
+  const uint32_t per = shifted ? 63u : 64u;
+  const uint32_t gpf = (quads + per - 1u) / per;
   const uint32_t items = F * gpf;
   const uint32_t w0 = wave_id(), nw = num_waves(), lane = lane_id();
   for (uint32_t it = w0; it < items; it += nw) {
     const uint32_t f = it / gpf;
-    const uint32_t q = (it - f * gpf) * 64u + lane;
-    // every lane takes part (the cross-lane shift below reads its neighbour);
-    // lanes past the tile read record 0 and store nothing
-    const bool act = q < quads;
-    const uint32_t r = act ? q * 4u : 0u;
+    const int qi = (int)((it - f * gpf) * per + lane) - (shifted ? 1 : 0);
+    // every lane takes part (the cross-lane read below needs its neighbour);
+    // lanes outside the tile read record 0 and store nothing
+    const bool act = qi >= 0 && qi < (int)quads;
+    const uint32_t q = act ? (uint32_t)qi : 0u;
+    const bool writer = act && !(shifted && lane == 0u);
+    const uint32_t r = q * 4u;
     uint32_t e[ES];
     read_elems4<ES, SL>(s, lds, r, f, e);
     uint32_t col[ES];  // col[k]: byte k of records r..r+3
@@ -626,7 +637,7 @@ __device__ __forceinline__ void store_split_fused(const Side& s, const Side& d, 
         for (int k = 0; k < 4; ++k) col[4 * h + k] = o[k];
       }
     }
-    const uint32_t nrec = !act ? 0u : (nt - r < 4u ? nt - r : 4u);
+    const uint32_t nrec = !writer ? 0u : (nt - r < 4u ? nt - r : 4u);
 #pragma unroll
     for (int k = 0; k < ES; ++k) {
       const uint32_t c = f * ES + k;
@@ -636,7 +647,7 @@ __device__ __forceinline__ void store_split_fused(const Side& s, const Side& d, 
       const uint64_t base = cb & ~15ull;
       const auto rs = make_rsrc((const uint8_t*)blob + base, d.blob_size - base);
       const uint32_t lo = (uint32_t)(cb - base) + col_local<DL>(d, r);
-      const uint32_t ph = (uint32_t)cb & 3u;  // run phase: nonzero only for a single-blob plane
+      const uint32_t ph = (uint32_t)cb & 3u;  // wave-uniform
       if (ph == 0u) {
         if (nrec == 4u) {
           __builtin_amdgcn_raw_buffer_store_b32(col[k], rs, lo, 0, 0);
@@ -645,24 +656,134 @@ __device__ __forceinline__ void store_split_fused(const Side& s, const Side& d, 
             __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(col[k] >> (8u * j)), rs, lo + j, 0, 0);
         }
       } else {
-        // lane l writes the aligned dword at lo - ph: the last ph bytes of
-        // lane l - 1 and its own first 4 - ph bytes.  Bytes whose dword has
-        // no complete owner (wave edges, the tile's last records) go out
-        // one by one, each by the lane holding it.
         const uint32_t prev = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((lane ? lane - 1u : 0u) * 4u), (int)col[k]);
-        const uint32_t lead = 4u - ph;  // own bytes in the dword at lo - ph
-        const bool full = lane > 0u && nrec >= lead;
-        const bool next_full = lane < 63u && r + 4u + lead <= nt;
-        if (full) {
+        const uint32_t lead = 4u - ph;       // own bytes in the dword at lo - ph
+        const bool has_prev = writer && q >= 1u;  // quad q - 1 is in the tile (it is lane l - 1's)
+        if (has_prev && nrec >= lead) {
           __builtin_amdgcn_raw_buffer_store_b32(__builtin_amdgcn_alignbyte(col[k], prev, lead), rs, lo - ph, 0, 0);
-        } else {
+        } else if (writer) {  // tile's first quad, or a short last quad
           for (uint32_t j = 0; j < lead && j < nrec; ++j)
             __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(col[k] >> (8u * j)), rs, lo + j, 0, 0);
+          if (has_prev)
+            for (uint32_t j = 0; j < ph; ++j)
+              __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(prev >> (8u * (lead + j))), rs, lo - ph + j, 0, 0);
         }
-        if (!next_full) {
+        // the tile's last quad: its last ph bytes have no owner in this tile
+        if (writer && q + 1u == quads)
           for (uint32_t j = lead; j < nrec; ++j)
             __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(col[k] >> (8u * j)), rs, lo + j, 0, 0);
+      }
+    }
+  }
+}
+
+// The 16-byte form of the split: a lane takes 16 consecutive records of one
+// field and stores one 16-byte run per byte plane, so a wave writes 1 KiB
+// contiguous per plane and store instruction.  Needs runs of 16 records per
+// column (planar, or AoSoA with L % 16 == 0).  A single-blob plane whose
+// start is off the 16-byte grid by ph bytes is written as aligned 16-byte
+// windows: the last ph bytes of the left neighbour's run (ds_bpermute) and
+// the lane's own first 16 - ph bytes.  As in the 4-byte form, lane 0 then
+// recomputes the run just before the wave's 63 writer runs, and only a
+// tile's first and last runs write single bytes.
+__device__ __forceinline__ u32x4 funnel16(const u32x4& p, const u32x4& o, uint32_t ph) {
+  // bytes [16 - ph, 32 - ph) of the 32-byte string p ++ o, for 0 < ph < 16
+  const uint32_t d[8] = {p.x, p.y, p.z, p.w, o.x, o.y, o.z, o.w};
+  const uint32_t sft = 16u - ph, dq = sft >> 2, rb = sft & 3u;
+  u32x4 v;
+  switch (dq) {  // wave-uniform
+#define LM_F(Q)                                                                                  \
+  case Q:                                                                                        \
+    v = u32x4{__builtin_amdgcn_alignbyte(d[Q + 1], d[Q], rb), __builtin_amdgcn_alignbyte(d[Q + 2], d[Q + 1], rb), \
+              __builtin_amdgcn_alignbyte(d[Q + 3], d[Q + 2], rb), __builtin_amdgcn_alignbyte(d[Q + 4], d[Q + 3], rb)}; \
+    break;
+    LM_F(0)
+    LM_F(1)
+    LM_F(2)
+    default: LM_F(3)
+#undef LM_F
+  }
+  return v;
+}
+
+template <int ES, int SL, int DL>
+__device__ __forceinline__ void store_split_fused16(const Side& s, const Side& d, uint64_t i0, uint32_t nt,
+                                                    const uint8_t* lds) {
+  const uint32_t F = s.ncols;
+  const uint32_t runs = (nt + 15u) >> 4;
+  const bool shifted = DL == LY_PLANAR && !d.mb && (d.n & 15u);
+  const uint32_t per = shifted ? 63u : 64u;
+  const uint32_t gpf = (runs + per - 1u) / per;
+  const uint32_t items = F * gpf;
+  const uint32_t w0 = wave_id(), nw = num_waves(), lane = lane_id();
+  for (uint32_t it = w0; it < items; it += nw) {
+    const uint32_t f = it / gpf;
+    const int qi = (int)((it - f * gpf) * per + lane) - (shifted ? 1 : 0);
+    const bool act = qi >= 0 && qi < (int)runs;
+    const uint32_t q = act ? (uint32_t)qi : 0u;
+    const bool writer = act && !(shifted && lane == 0u);
+    const uint32_t r = q * 16u;
+    uint32_t col[ES][4];  // col[k][m]: byte k of records r + 4m .. r + 4m + 3
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      uint32_t e[ES];
+      read_elems4<ES, SL>(s, lds, r + 4u * m, f, e);
+      if constexpr (ES == 2) {
+        col[0][m] = __builtin_amdgcn_perm(e[1], e[0], 0x06040200u);
+        col[1][m] = __builtin_amdgcn_perm(e[1], e[0], 0x07050301u);
+      } else {
+        constexpr int DW = ES / 4;
+#pragma unroll
+        for (int h = 0; h < DW; ++h) {
+          uint32_t in[4], o[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) in[j] = e[j * DW + h];
+          transpose4x4(in, o);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) col[4 * h + k][m] = o[k];
         }
+      }
+    }
+    const uint32_t nrec = !writer ? 0u : (nt - r < 16u ? nt - r : 16u);
+#pragma unroll
+    for (int k = 0; k < ES; ++k) {
+      const uint32_t c = f * ES + k;
+      const void* blob = (DL == LY_PLANAR && d.mb) ? d.blob[c] : d.blob[0];
+      const uint64_t cb = col_base<DL>(d, i0, c);
+      const uint64_t base = cb & ~15ull;
+      const auto rs = make_rsrc((const uint8_t*)blob + base, d.blob_size - base);
+      const uint32_t lo = (uint32_t)(cb - base) + col_local<DL>(d, r);
+      const uint32_t ph = (uint32_t)cb & 15u;  // wave-uniform
+      const u32x4 own = u32x4{col[k][0], col[k][1], col[k][2], col[k][3]};
+      auto own_byte = [&](uint32_t j) { return (uint8_t)(col[k][j >> 2] >> (8u * (j & 3u))); };
+      if (ph == 0u) {
+        if (nrec == 16u) {
+          __builtin_amdgcn_raw_buffer_store_b128(own, rs, lo, 0, 0);
+        } else {
+          for (uint32_t j = 0; j < nrec; ++j) __builtin_amdgcn_raw_buffer_store_b8(own_byte(j), rs, lo + j, 0, 0);
+        }
+      } else {
+        const int src_lane = (int)((lane ? lane - 1u : 0u) * 4u);
+        const u32x4 prev = u32x4{(uint32_t)__builtin_amdgcn_ds_bpermute(src_lane, (int)own.x),
+                                 (uint32_t)__builtin_amdgcn_ds_bpermute(src_lane, (int)own.y),
+                                 (uint32_t)__builtin_amdgcn_ds_bpermute(src_lane, (int)own.z),
+                                 (uint32_t)__builtin_amdgcn_ds_bpermute(src_lane, (int)own.w)};
+        const uint32_t lead = 16u - ph;       // own bytes in the window at lo - ph
+        const bool has_prev = writer && q >= 1u;  // run q - 1 is in the tile (lane l - 1's)
+        if (has_prev && nrec >= lead) {
+          __builtin_amdgcn_raw_buffer_store_b128(funnel16(prev, own, ph), rs, lo - ph, 0, 0);
+        } else if (writer) {  // the tile's first run, or a short last run
+          for (uint32_t j = 0; j < lead && j < nrec; ++j)
+            __builtin_amdgcn_raw_buffer_store_b8(own_byte(j), rs, lo + j, 0, 0);
+          if (has_prev)
+            for (uint32_t j = 0; j < ph; ++j) {
+              const uint32_t b = lead + j;  // byte of the neighbour's run
+              __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(prev[b >> 2] >> (8u * (b & 3u))), rs, lo - ph + j, 0, 0);
+            }
+        }
+        // the tile's last run: its last ph bytes have no owner in this tile
+        if (writer && q + 1u == runs)
+          for (uint32_t j = lead; j < nrec; ++j) __builtin_amdgcn_raw_buffer_store_b8(own_byte(j), rs, lo + j, 0, 0);
       }
     }
   }
