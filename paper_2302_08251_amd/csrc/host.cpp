@@ -470,13 +470,15 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     // Byte planes (a planar Bytesplit side) need longer tiles to fill whole
     // 1 KiB wave groups: about 30 KiB with one such side, 24 KiB with two.
     // Pack holds the source tile and its stream-word image in LDS: about
-    // 24 KiB in all.  Unpack writes its (larger) output from registers, so
-    // only its stream tile counts: about 16 KiB, up to a 64 KiB output tile.
+    // 24 KiB in all.  Unpack writes its (larger) output from registers:
+    // about 8 KiB of stream words, up to a 16 KiB output tile.
     const bool bs = S.layout == LY_PLANAR && S.cs == 1, bd = D.layout == LY_PLANAR && D.cs == 1;
     // AoS to AoS (a straight 16-byte copy through LDS) is fastest with short
     // tiles: about 7 KiB.
     const bool aos2aos = plan.kind == PK_RAW && mode == RM_DIRECT && S.layout == LY_AOS && D.layout == LY_AOS;
+    const bool unpack = plan.kind == PK_UNPACK;
     const uint64_t target = pack ? 24576
+                            : unpack ? 8192
                             : plan.kind == PK_CONV ? 32768  // ChangeType: 32 KiB on the wider side
                             : aos2aos ? 7168
                             : canonical ? 32768
@@ -486,7 +488,8 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     uint64_t per = plan.kind == PK_UNPACK ? lds_total(gran) : std::max<uint64_t>(lds_total(gran), gran * dst_bytes);
     uint64_t k = per ? (target / per) : 1;
     if (k < 1) k = 1;
-    while (k > 1 && (gran * k > 65536 || gran * k * dst_bytes > 65536)) --k;
+    const uint64_t dst_cap = unpack ? 16384 : 65536;
+    while (k > 1 && (gran * k > 65536 || gran * k * dst_bytes > dst_cap)) --k;
     while (lds_cap && k > 1 && lds_total(gran * k) > lds_cap) --k;
     if (fill && lds_cap) {  // grow the tile to the largest one within the cap
       while (gran * (k + 1) <= 65536 && lds_total(gran * (k + 1)) <= lds_cap &&

@@ -1152,9 +1152,43 @@ __device__ __forceinline__ void store_pack(const Side& s, const Side& d, uint64_
 // Phase B, unpack from bit streams into a physical layout
 // ---------------------------------------------------------------------------
 
+// Unpack into element planes of 4-byte values: a lane decodes four
+// consecutive values of one field straight from the stream words and stores
+// them as one 16-byte chunk (a wave writes 1 KiB contiguous).  Used when the
+// plane's tile run starts on the 16-byte grid; the generic gather below
+// handles every other destination.
+template <int CODEC>
+__device__ __forceinline__ void store_unpack_planar4(const Side& s, const Side& d, uint64_t i0, uint32_t nt,
+                                                     const uint8_t* lds, uint32_t f) {
+  const uint32_t B = s.bits;
+  const uint32_t quads = (nt + 3u) >> 2;
+  const uint64_t start = seg_start(d, f, i0);
+  const auto rs = make_rsrc((const uint8_t*)seg_blob(d, f) + start, d.blob_size - start);
+  const uint8_t* plane = lds + f * s.lds_stride;
+  for (uint32_t q = threadIdx.x; q < quads; q += blockDim.x) {
+    const uint32_t r = 4u * q;
+    uint32_t v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = (uint32_t)decode<CODEC>(stream_code(plane, r + k, B), s);
+    if (r + 4u <= nt) {
+      __builtin_amdgcn_raw_buffer_store_b128(u32x4{v[0], v[1], v[2], v[3]}, rs, 16u * q, 0, kStoreNT);
+    } else {
+      for (uint32_t k = 0; r + k < nt; ++k) __builtin_amdgcn_raw_buffer_store_b32(v[k], rs, 16u * q + 4u * k, 0, 0);
+    }
+  }
+}
+
 template <int CODEC, int U, int DL>
 __device__ __forceinline__ void store_unpack(const Side& s, const Side& d, uint64_t i0, uint32_t nt,
                                              const uint8_t* lds) {
+  if constexpr (DL == LY_PLANAR && U == 4 && CodecInfo<CODEC>::ES == 4) {
+    // every field's run must start on the 16-byte grid (single-blob planes
+    // start at f * 4n)
+    if (d.mb || (d.n & 3u) == 0u) {
+      for (uint32_t f = 0; f < d.ncols; ++f) store_unpack_planar4<CODEC>(s, d, i0, nt, lds, f);
+      return;
+    }
+  }
   constexpr int NU = 16 / U;
   constexpr uint32_t FULL = (1u << NU) - 1u;
   constexpr int ES = CodecInfo<CODEC>::ES;
