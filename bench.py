@@ -52,8 +52,20 @@ class Timer:
     def __init__(self, torch):
         self.torch = torch
 
-    def time(self, fn, reps):
+    def warm(self, fn, seconds=0.2):
+        """Runs fn until `seconds` of GPU work have passed: after CPU-side input
+        generation the GPU needs that long to return to its steady clocks."""
         t = self.torch
+        t.cuda.synchronize()
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < seconds:
+            fn()
+            t.cuda.synchronize()
+
+    def time(self, fn, reps, warm=True):
+        t = self.torch
+        if warm:
+            self.warm(fn)
         evs = [(t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)) for _ in range(reps)]
         for a, b in evs:
             a.record()
@@ -119,13 +131,13 @@ def bench_cfg2(lm, torch, steps, warmup, n):
 
     for _ in range(warmup):
         step()
-    torch.cuda.synchronize()
+    T.warm(step)
     per_pair = {f"{a}->{b}": [] for a, b in pairs}
     step_ms = []
     for _ in range(steps):
         ts = []
         for a, b in pairs:
-            ms = T.time(lambda: lm.llama_copy(src[a], dst[b]), 1)[0]
+            ms = T.time(lambda: lm.llama_copy(src[a], dst[b]), 1, warm=False)[0]
             per_pair[f"{a}->{b}"].append(ms)
             ts.append(ms)
         step_ms.append(sum(ts))
@@ -297,9 +309,10 @@ def bench_cfg5(lm, torch, n, steps):
         lm.llama_pack(mb, v)
         e0 = lm.nbody_energy(v, 0.01)
         lm.nbody_step(v, 1, 1e-4, 0.01)
-        ts = T.time(lambda: lm.nbody_step(v, 1, 1e-4, 0.01), steps)
+        T.warm(lambda: lm.nbody_energy(v, 0.01))  # steady clocks without moving the particles
+        ts = T.time(lambda: lm.nbody_step(v, 1, 1e-4, 0.01), steps, warm=False)
         e1 = lm.nbody_energy(v, 0.01)
-        te = T.time(lambda: lm.nbody_energy(v, 0.01), 2)
+        te = T.time(lambda: lm.nbody_energy(v, 0.01), 2, warm=False)
         ms = float(np.median(ts))
         inter = float(n) * n
         out[name] = {"ms_per_step": ms, "interactions_per_s": inter / (ms * 1e-3),
