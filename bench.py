@@ -192,6 +192,18 @@ def bench_cfg3(lm, torch, reps, n_vals, n_rec):
         out[f"float_e{E}m{M}"] = {"pack_gbs": alg / tp / 1e6, "unpack_gbs": alg / tu / 1e6,
                                   "pack_ms": tp, "unpack_ms": tu, "alg_bytes": alg}
         c.close()
+    # ChangeType into half formats on the same values (narrowing RNE / exact widening)
+    for stored in ("f16", "bf16"):
+        c = lm.View(["f32"], {"kind": "changetype", "stored": [stored], "inner": {"kind": "soa_mb"}}, [n_vals],
+                    index_type="u32")
+        lm.llama_pack(src, c)
+        lm.llama_unpack(c, back)
+        alg = 6 * n_vals
+        tp = float(np.median(T.time(lambda: lm.llama_pack(src, c), reps)))
+        tu = float(np.median(T.time(lambda: lm.llama_unpack(c, back), reps)))
+        out[f"changetype_f32_{stored}"] = {"pack_gbs": alg / tp / 1e6, "unpack_gbs": alg / tu / 1e6,
+                                           "pack_ms": tp, "unpack_ms": tu, "alg_bytes": alg}
+        c.close()
     log("cfg3: int pack/unpack B=3..31")
     g = torch.Generator(device="cuda").manual_seed(0)
     u = torch.randint(0, 2 ** 31, (n_vals,), generator=g, device="cuda", dtype=torch.int64).to(torch.int32)

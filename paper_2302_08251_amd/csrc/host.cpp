@@ -437,9 +437,19 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     const llama_scalar to = D.vkind == VK_CONV ? ds : du;
     plan.kind = PK_CONV;
     plan.unit = D.cs;
-    if (from == LLAMA_F64 && to == LLAMA_F32) plan.args.conv = CV_F64_F32;
-    else if (from == LLAMA_F32 && to == LLAMA_F64) plan.args.conv = CV_F32_F64;
-    else return fail(LLAMA_ERR_UNSUPPORTED, "the GPU path converts between F64 and F32 only");
+    struct Pair { llama_scalar from, to; Conv cv; };
+    static const Pair pairs[] = {
+        {LLAMA_F64, LLAMA_F32, CV_F64_F32},   {LLAMA_F32, LLAMA_F64, CV_F32_F64},
+        {LLAMA_F32, LLAMA_F16, CV_F32_F16},   {LLAMA_F32, LLAMA_BF16, CV_F32_BF16},
+        {LLAMA_F64, LLAMA_F16, CV_F64_F16},   {LLAMA_F64, LLAMA_BF16, CV_F64_BF16},
+        {LLAMA_F16, LLAMA_F32, CV_F16_F32},   {LLAMA_BF16, LLAMA_F32, CV_BF16_F32},
+        {LLAMA_F16, LLAMA_F64, CV_F16_F64},   {LLAMA_BF16, LLAMA_F64, CV_BF16_F64},
+    };
+    plan.args.conv = CV_NONE;
+    for (const Pair& q : pairs)
+      if (q.from == from && q.to == to) plan.args.conv = q.cv;
+    if (plan.args.conv == CV_NONE)
+      return fail(LLAMA_ERR_UNSUPPORTED, "the GPU path converts between the float types f64, f32, f16 and bf16 only");
   }
   const uint32_t mode = plan.kind == PK_RAW ? plan.args.mode : RM_DIRECT;
   const bool canonical = mode == RM_MERGE || mode == RM_SPLIT;

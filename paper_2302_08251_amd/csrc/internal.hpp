@@ -68,6 +68,14 @@ enum Conv : uint32_t {
   CV_NONE = 0,
   CV_F64_F32 = 1,  // narrowing, round to nearest even
   CV_F32_F64 = 2,  // widening, exact
+  CV_F32_F16 = 3,  // the rest: narrowing (RNE) or widening (exact) through
+  CV_F32_BF16 = 4, //   the generic IEEE conversions
+  CV_F64_F16 = 5,
+  CV_F64_BF16 = 6,
+  CV_F16_F32 = 7,
+  CV_BF16_F32 = 8,
+  CV_F16_F64 = 9,
+  CV_BF16_F64 = 10,
 };
 
 // Bit-packed codecs by user element type.

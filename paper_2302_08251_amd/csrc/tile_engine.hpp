@@ -896,6 +896,71 @@ __device__ __forceinline__ uint64_t cvt_f32_f64(uint32_t x) {
   return nan ? rn : r;
 }
 
+// Generic ChangeType conversions between IEEE binary formats given by their
+// exponent and mantissa widths (f64 11/52, f32 8/23, f16 5/10, bf16 8/7).
+//
+// Narrowing rounds to nearest, ties to even.  The value is the source
+// significand (hidden bit at MS) scaled by its exponent; it is shifted so the
+// hidden bit lands on bit MD, or lower for a target subnormal, and the
+// dropped bits decide the rounding.  Adding (exponent - 1) << MD to a
+// significand that still carries its hidden bit lets a rounding carry move
+// into the exponent by itself.  Codes at or past the Inf code become Inf.
+// A NaN keeps its sign and top MD payload bits and gets the quiet bit.
+template <int ES, int MS, int ED, int MD>
+__device__ __forceinline__ uint64_t narrow_rne(uint64_t x) {
+  constexpr int emax_s = (1 << ES) - 1, emax_d = (1 << ED) - 1;
+  constexpr int bias_s = (1 << (ES - 1)) - 1, bias_d = (1 << (ED - 1)) - 1;
+  const uint64_t sign = (x >> (ES + MS)) & 1ull;
+  const uint64_t m = x & ((1ull << MS) - 1ull);
+  const int es = (int)((x >> MS) & (uint64_t)emax_s);
+  uint64_t code;
+  if (es == emax_s) {
+    code = ((uint64_t)emax_d << MD) | (m ? ((m >> (MS - MD)) | (1ull << (MD - 1))) : 0ull);
+  } else {
+    const uint64_t sig = es ? (m | (1ull << MS)) : m;
+    const int ed = (es ? es : 1) - bias_s + bias_d;  // target exponent field of the hidden-bit position
+    const int sh = MS - MD + (ed < 1 ? 1 - ed : 0);  // >= 1: the formats narrow
+    uint64_t q = 0;
+    if (sh <= MS + 1) {  // otherwise the value is below half the smallest subnormal
+      q = sig >> sh;
+      const uint64_t rem = sig & ((1ull << sh) - 1ull), half = 1ull << (sh - 1);
+      q += (rem > half || (rem == half && (q & 1ull))) ? 1ull : 0ull;
+    }
+    code = ed >= 1 ? ((uint64_t)(ed - 1) << MD) + q : q;
+    const uint64_t inf = (uint64_t)emax_d << MD;
+    code = code >= inf ? inf : code;
+  }
+  return code | (sign << (ED + MD));
+}
+
+// Widening is exact: a source subnormal becomes a target normal when the
+// target exponent range is wider (a subnormal when it is the same); a NaN's
+// payload moves up and the quiet bit is set.
+template <int ES, int MS, int ED, int MD>
+__device__ __forceinline__ uint64_t widen(uint64_t x) {
+  constexpr int emax_s = (1 << ES) - 1, emax_d = (1 << ED) - 1;
+  constexpr int bias_s = (1 << (ES - 1)) - 1, bias_d = (1 << (ED - 1)) - 1;
+  const uint64_t sign = (x >> (ES + MS)) & 1ull;
+  const uint64_t m = x & ((1ull << MS) - 1ull);
+  const int es = (int)((x >> MS) & (uint64_t)emax_s);
+  uint64_t code;
+  if (es == emax_s) {
+    code = ((uint64_t)emax_d << MD) | (m << (MD - MS)) | (m ? (1ull << (MD - 1)) : 0ull);
+  } else if (es == 0) {
+    if (m == 0) {
+      code = 0;
+    } else if constexpr (ED == ES) {  // same exponent range: still a subnormal
+      code = m << (MD - MS);
+    } else {  // m * 2^(1 - bias_s - MS), a normal of the wider range
+      const int p = 63 - __builtin_clzll(m);
+      code = ((uint64_t)(p + 1 - bias_s - MS + bias_d) << MD) | ((m ^ (1ull << p)) << (MD - p));
+    }
+  } else {
+    code = ((uint64_t)(es - bias_s + bias_d) << MD) | (m << (MD - MS));
+  }
+  return code | (sign << (ED + MD));
+}
+
 // BitPackedFloatSoA codes (Sec. 3): [sign | E | M], bias 2^(E-1)-1,
 // mantissa truncated, overflow -> Inf, gradual underflow, NaN kept quiet.
 __device__ __forceinline__ uint32_t enc_f32(uint32_t x, uint32_t E, uint32_t M) {
@@ -1031,14 +1096,26 @@ __device__ __forceinline__ uint32_t stream_code(const uint8_t* plane, uint32_t r
 
 template <int CONV>
 struct ConvInfo {
-  static constexpr int ES_SRC = CONV == CV_F64_F32 ? 8 : 4;
-  static constexpr int ES_DST = CONV == CV_F64_F32 ? 4 : 8;
+  static constexpr int ES_SRC = (CONV == CV_F64_F32 || CONV == CV_F64_F16 || CONV == CV_F64_BF16) ? 8
+                                : (CONV == CV_F32_F64 || CONV == CV_F32_F16 || CONV == CV_F32_BF16) ? 4
+                                                                                                     : 2;
+  static constexpr int ES_DST = (CONV == CV_F32_F64 || CONV == CV_F16_F64 || CONV == CV_BF16_F64) ? 8
+                                : (CONV == CV_F64_F32 || CONV == CV_F16_F32 || CONV == CV_BF16_F32) ? 4
+                                                                                                     : 2;
 };
 
 template <int CONV>
 __device__ __forceinline__ uint64_t convert(uint64_t v) {
   if constexpr (CONV == CV_F64_F32) return cvt_f64_f32(v);
-  else return cvt_f32_f64((uint32_t)v);
+  else if constexpr (CONV == CV_F32_F64) return cvt_f32_f64((uint32_t)v);
+  else if constexpr (CONV == CV_F32_F16) return narrow_rne<8, 23, 5, 10>(v);
+  else if constexpr (CONV == CV_F32_BF16) return narrow_rne<8, 23, 8, 7>(v);
+  else if constexpr (CONV == CV_F64_F16) return narrow_rne<11, 52, 5, 10>(v);
+  else if constexpr (CONV == CV_F64_BF16) return narrow_rne<11, 52, 8, 7>(v);
+  else if constexpr (CONV == CV_F16_F32) return widen<5, 10, 8, 23>(v);
+  else if constexpr (CONV == CV_BF16_F32) return widen<8, 7, 8, 23>(v);
+  else if constexpr (CONV == CV_F16_F64) return widen<5, 10, 11, 52>(v);
+  else return widen<8, 7, 11, 52>(v);
 }
 
 template <int CONV, int U, int DL, int SL>
@@ -1047,7 +1124,7 @@ __device__ __forceinline__ void store_conv(const Side& s, const Side& d, uint64_
   constexpr int NU = 16 / U;
   constexpr uint32_t FULL = (1u << NU) - 1u;
   constexpr int ESS = ConvInfo<CONV>::ES_SRC, ESD = ConvInfo<CONV>::ES_DST;
-  constexpr int LOG_ESD = ESD == 8 ? 3 : 2;
+  constexpr int LOG_ESD = ESD == 8 ? 3 : ESD == 4 ? 2 : 1;
   for_dst_chunks(d, i0, nt, [&](__amdgpu_buffer_rsrc_t rs, uint32_t seg, uint32_t off, int x0, uint32_t len) {
     uint32_t w[4] = {0u, 0u, 0u, 0u};
     uint32_t valid = 0;

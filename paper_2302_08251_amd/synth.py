@@ -106,3 +106,35 @@ def batch_views(count=2000, seed=0, lo=1e3, hi=4e6, n_pairs=30):
     n = np.rint(np.exp(rng.uniform(np.log(lo), np.log(hi), count))).astype(np.int64)
     pairs = rng.integers(0, n_pairs, count)
     return n, pairs
+
+
+def narrow_range_values(n, seed=0, dtype=np.float32):
+    """One plane (as unsigned bit patterns) of values around the f16 / bf16
+    ranges: log-uniform magnitudes over 2^-30 .. 2^20 with random signs; a
+    quarter of them with the mantissa bits below a 10- or 7-bit mantissa set
+    to exactly half a unit (rounding ties); then the special-value mix."""
+    rng = np.random.default_rng(seed)
+    mag = np.exp2(rng.uniform(-30.0, 20.0, n)).astype(dtype)
+    vals = np.where(rng.integers(0, 2, n) == 1, -mag, mag).astype(dtype)
+    if dtype == np.float32:
+        bits = vals.view(np.uint32).copy()
+        drop = np.where(rng.integers(0, 2, n) == 1, 13, 16).astype(np.uint32)
+        one = np.uint32(1)
+    else:
+        bits = vals.view(np.uint64).copy()
+        drop = np.where(rng.integers(0, 2, n) == 1, 42, 45).astype(np.uint64)
+        one = np.uint64(1)
+    tie = rng.random(n) < 0.25
+    low = (one << drop) - one
+    bits[tie] = (bits[tie] & ~low[tie]) | (one << (drop[tie] - one))
+    if dtype == np.float32:
+        return _special_mix_f32_bits(rng, n, bits)
+    # f64: ~1 % each of infinities, NaNs with random payloads, denormals
+    u = rng.random(n)
+    sign = rng.integers(0, 2, n, dtype=np.uint64) << np.uint64(63)
+    mant = rng.integers(1, 1 << 52, n, dtype=np.uint64)
+    inf, nan, den = u < 0.01, (u >= 0.01) & (u < 0.02), (u >= 0.02) & (u < 0.03)
+    bits[inf] = sign[inf] | np.uint64(0x7FF0000000000000)
+    bits[nan] = sign[nan] | np.uint64(0x7FF0000000000000) | mant[nan]
+    bits[den] = sign[den] | mant[den]
+    return bits

@@ -56,6 +56,24 @@ def test_changetype_f32_user_f64_storage(n):
             pack_unpack(rec, phys, comp, n, planes)
 
 
+@pytest.mark.parametrize("user,stored", [("f32", "f16"), ("f32", "bf16"), ("f64", "f16"), ("f64", "bf16")])
+@pytest.mark.parametrize("n", [1, 100, 4097])
+def test_changetype_half_formats(user, stored, n):
+    """ChangeType storage in f16 / bf16 (narrowing with round to nearest even on
+    pack, exact widening on unpack): values around the half formats' ranges
+    with rounding ties, NaN payloads, infinities, denormals, and uniformly
+    random bit patterns."""
+    dt = np.float32 if user == "f32" else np.float64
+    rec = [user] * 3
+    planes = [synth.narrow_range_values(n, seed=n + f, dtype=dt).view(dt) for f in range(2)]
+    planes.append(synth.random_bit_planes(n, 1, seed=n, bits=32 if user == "f32" else 64)[0].view(dt))
+    for inner in PHYS:
+        comp = {"kind": "changetype", "stored": [stored] * 3, "inner": inner}
+        for phys in (PHYS[0], PHYS[1], PHYS[4]):
+            say("ct-half", user, stored, phys, inner, n)
+            pack_unpack(rec, phys, comp, n, planes)
+
+
 @pytest.mark.parametrize("n", [1, 77, 1000, 4500])
 def test_bitpack_int_all_widths_i32_u32(n):
     for t in ("i32", "u32"):
