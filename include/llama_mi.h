@@ -118,6 +118,13 @@ typedef enum llama_map_kind {
 } llama_map_kind;
 
 #define LLAMA_FLAG_AOS_PACKED 0x1u /* AOS: no alignment padding between fields */
+#define LLAMA_FLAG_ROUND_RNE 0x2u  /* BITPACK_FLOAT: round the mantissa to nearest,
+                                      ties to even (ties compare the
+                                      significand's last bit: with M = 0 the
+                                      hidden bit, so a tie rounds away from
+                                      zero), instead of truncating it; a value
+                                      that rounds past the largest finite code
+                                      gives +-Inf.  Other mappings: INVALID_ARG. */
 
 typedef struct llama_mapping {
   llama_map_kind kind;

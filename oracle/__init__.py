@@ -36,7 +36,7 @@ class _Map(C.Structure):
 
 _Map._fields_ = [("kind", C.c_int), ("lanes", C.c_uint32), ("bits", C.c_uint32),
                  ("exp_bits", C.c_uint32), ("man_bits", C.c_uint32), ("aos_packed", C.c_int),
-                 ("stored_types", C.POINTER(C.c_int)), ("inner", C.POINTER(_Map))]
+                 ("stored_types", C.POINTER(C.c_int)), ("inner", C.POINTER(_Map)), ("round_rne", C.c_int)]
 
 _lib = None
 
@@ -79,7 +79,7 @@ def lib():
         L.orc_convert_array.restype = None
         L.orc_convert_array.argtypes = [C.c_void_p, i32, C.c_void_p, i32, u64, i32]
         L.orc_float_encode_array.restype = None
-        L.orc_float_encode_array.argtypes = [C.c_void_p, i32, u32, u32, C.c_void_p, u64, i32]
+        L.orc_float_encode_array.argtypes = [C.c_void_p, i32, u32, u32, C.c_void_p, u64, i32, i32]
         L.orc_float_decode_array.restype = None
         L.orc_float_decode_array.argtypes = [C.c_void_p, i32, u32, u32, C.c_void_p, u64, i32]
         L.orc_nbody.restype = None
@@ -115,6 +115,7 @@ def _map(spec, keep):
     m.exp_bits = spec.get("exp", 0)
     m.man_bits = spec.get("man", 0)
     m.aos_packed = 1 if spec.get("packed", False) else 0
+    m.round_rne = 1 if spec.get("round") == "rne" else 0
     if "stored" in spec:
         arr = (C.c_int * len(spec["stored"]))(*[_TYPES[t] for t in spec["stored"]])
         keep.objs.append(arr)
@@ -237,10 +238,10 @@ def float_decode(code, t, E, M):
     return lib().orc_float_decode(int(code), _TYPES[t], E, M)
 
 
-def float_encode_array(a, t, E, M, threads=0):
+def float_encode_array(a, t, E, M, threads=0, rne=False):
     a = np.ascontiguousarray(a)
     out = np.zeros(len(a), np.uint64)
-    lib().orc_float_encode_array(a.ctypes.data, _TYPES[t], E, M, out.ctypes.data, len(a), threads)
+    lib().orc_float_encode_array(a.ctypes.data, _TYPES[t], E, M, out.ctypes.data, len(a), threads, int(rne))
     return out
 
 

@@ -199,11 +199,19 @@ EXPORT int orc_conversion_supported(int from, int to) {
 
 EXPORT uint64_t orc_convert(uint64_t bits, int from, int to) { return convert_value(bits, from, to); }
 
-/* BitPackedFloat code of a value of float type t (E <= E_t, M <= M_t). */
+/* BitPackedFloat code of a value of float type t (E <= E_t, M <= M_t).  The
+ * mantissa is truncated (Sec. 3 leaves the rounding open); the _rne variant
+ * rounds it to nearest, ties to even, the opt-in mode of the mapping. */
 EXPORT uint64_t orc_float_encode(uint64_t bits, int t, uint32_t E, uint32_t M) {
   uint32_t Et, Mt;
   float_format(t, &Et, &Mt);
   return ieee_narrow(bits, Et, Mt, E, M, 0);
+}
+
+EXPORT uint64_t orc_float_encode_rne(uint64_t bits, int t, uint32_t E, uint32_t M) {
+  uint32_t Et, Mt;
+  float_format(t, &Et, &Mt);
+  return ieee_narrow(bits, Et, Mt, E, M, 1);
 }
 
 EXPORT uint64_t orc_float_decode(uint64_t code, int t, uint32_t E, uint32_t M) {
@@ -409,7 +417,9 @@ EXPORT void orc_store(const orc_rec* rec, const orc_map* m, uint64_t n, uint8_t*
       return;
     case ORC_BITPACK_FLOAT: {
       uint32_t B = code_bits(m);
-      stream_put(blobs[f], i * B, B, orc_float_encode(v, t, m->exp_bits, m->man_bits));
+      stream_put(blobs[f], i * B, B,
+                 m->round_rne ? orc_float_encode_rne(v, t, m->exp_bits, m->man_bits)
+                              : orc_float_encode(v, t, m->exp_bits, m->man_bits));
       return;
     }
   }
@@ -487,14 +497,16 @@ EXPORT void orc_convert_array(const void* in, int from, void* out, int to, uint6
 
 /* codes are stored one per uint64 for arrays */
 EXPORT void orc_float_encode_array(const void* in, int t, uint32_t E, uint32_t M, uint64_t* codes,
-                                   uint64_t n, int threads) {
+                                   uint64_t n, int threads, int rne) {
   const uint32_t s = orc_type_size(t);
 #ifdef _OPENMP
   if (threads <= 0) threads = omp_get_max_threads();
 #pragma omp parallel for schedule(static) num_threads(threads)
 #endif
-  for (int64_t i = 0; i < (int64_t)n; ++i)
-    codes[i] = orc_float_encode(read_elem(in, s, (uint64_t)i), t, E, M);
+  for (int64_t i = 0; i < (int64_t)n; ++i) {
+    const uint64_t v = read_elem(in, s, (uint64_t)i);
+    codes[i] = rne ? orc_float_encode_rne(v, t, E, M) : orc_float_encode(v, t, E, M);
+  }
 }
 
 EXPORT void orc_float_decode_array(const uint64_t* codes, int t, uint32_t E, uint32_t M, void* out,

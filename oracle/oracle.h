@@ -31,6 +31,8 @@ typedef struct orc_map {
   int aos_packed;      /* AoS without padding      */
   const int* stored_types;       /* ChangeType    */
   const struct orc_map* inner;   /* Bytesplit / ChangeType */
+  int round_rne;       /* BitPackedFloat: round the mantissa to nearest even
+                          instead of truncating it */
 } orc_map;
 
 #endif

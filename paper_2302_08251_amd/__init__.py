@@ -36,6 +36,7 @@ INDEX_TYPES = {"i16": 0, "u16": 1, "i32": 2, "u32": 3, "i64": 4, "u64": 5}
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "UNSUPPORTED", -3: "INDEX_OVERFLOW",
           -4: "RECORD_MISMATCH", -5: "ALIGNMENT", -6: "HIP", -7: "NO_MEMORY"}
 FLAG_AOS_PACKED = 1
+FLAG_ROUND_RNE = 0x2
 
 
 class LlamaError(RuntimeError):
@@ -142,7 +143,7 @@ def _mapping(spec, keep):
     m.bits = spec.get("bits", 0)
     m.exp_bits = spec.get("exp", 0)
     m.man_bits = spec.get("man", 0)
-    m.flags = FLAG_AOS_PACKED if spec.get("packed") else 0
+    m.flags = (FLAG_AOS_PACKED if spec.get("packed") else 0) | (FLAG_ROUND_RNE if spec.get("round") == "rne" else 0)
     if "stored" in spec:
         arr = (C.c_int * len(spec["stored"]))(*[SCALARS[t] for t in spec["stored"]])
         keep.append(arr)

@@ -87,7 +87,10 @@ llama_status copy_mapping(const Rec& rec, const llama_mapping* map, MapDesc& out
   out.exp_bits = map->exp_bits;
   out.man_bits = map->man_bits;
   out.flags = map->flags;
-  if (map->flags & ~LLAMA_FLAG_AOS_PACKED) return fail(LLAMA_ERR_INVALID_ARG, "unknown mapping flags");
+  if (map->flags & ~(LLAMA_FLAG_AOS_PACKED | LLAMA_FLAG_ROUND_RNE))
+    return fail(LLAMA_ERR_INVALID_ARG, "unknown mapping flags");
+  if ((map->flags & LLAMA_FLAG_ROUND_RNE) && map->kind != LLAMA_MAP_BITPACK_FLOAT_SOA)
+    return fail(LLAMA_ERR_INVALID_ARG, "LLAMA_FLAG_ROUND_RNE applies to BITPACK_FLOAT_SOA only");
   switch (map->kind) {
     case LLAMA_MAP_AOS:
     case LLAMA_MAP_SOA_SB:
@@ -322,6 +325,7 @@ llama_status make_side(const llama_view* v, Side& s, llama_scalar& user_t, llama
       s.bits = code_bits(m);
       s.exp_bits = m.exp_bits;
       s.man_bits = m.man_bits;
+      s.rne = (m.flags & LLAMA_FLAG_ROUND_RNE) ? 1u : 0u;
       s.is_signed = scalar_is_signed(user_t);
       s.ncols = nf;
       s.cs = 4;

@@ -52,7 +52,7 @@ struct Side {
   uint32_t is_signed;  // VK_INT: sign-extend on decode
   uint32_t lds_stride; // planar / stream: LDS bytes per column or field plane
   uint32_t n_mod16;    // n mod 16 (phase of single-blob planes)
-  uint32_t pad0;
+  uint32_t rne;        // stream: float codes round to nearest even (else truncate)
   uint64_t n;          // records
   uint64_t blob_size;  // bytes the mapping uses in each blob (all blobs of a side are equal)
   Div div_S;           // S

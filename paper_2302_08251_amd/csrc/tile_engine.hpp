@@ -990,6 +990,60 @@ __device__ __forceinline__ uint32_t enc_f32(uint32_t x, uint32_t E, uint32_t M) 
   return c | ((x >> 31) << (E + M));
 }
 
+// Round-to-nearest-even forms (mapping flag): the dropped mantissa bits of a
+// target normal round the code up (a carry moves into the exponent, past the
+// largest finite code to Inf); a target subnormal is the scaled magnitude
+// rounded to the nearest integer, ties to even (exact scaling, rint).  Ties
+// compare the significand's last bit: the mantissa's, or the hidden bit when
+// M = 0, which rounds a tie away from zero.
+__device__ __forceinline__ uint32_t enc_f32_rne(uint32_t x, uint32_t E, uint32_t M) {
+  const uint32_t sh = 23u - M;
+  const uint32_t bias = (1u << (E - 1u)) - 1u;
+  const uint32_t emin = 128u - bias;
+  const uint32_t inf_code = ((1u << E) - 1u) << M;
+  const uint32_t ax = x & 0x7FFFFFFFu;
+  const uint32_t t = ax >> sh;
+  const uint32_t rem = ax & ((1u << sh) - 1u), half = sh ? (1u << (sh - 1u)) : 0u;
+  const uint32_t odd = M ? (t & 1u) : 1u;
+  const uint32_t up = (sh != 0u) && (rem > half || (rem == half && odd)) ? 1u : 0u;
+  const uint32_t c_norm = min(t + up - ((emin - 1u) << M), inf_code);
+  const uint32_t k = bias + M - 1u;
+  const uint32_t k1 = k < 127u ? k : 127u;
+  const float s1 = __builtin_bit_cast(float, (k1 + 127u) << 23), s2 = __builtin_bit_cast(float, (k - k1 + 127u) << 23);
+  const float mag = __builtin_bit_cast(float, ax) * s1 * s2;
+  const uint32_t c_sub = ax < (emin << 23) ? (uint32_t)__builtin_rintf(mag) : 0u;
+  const uint32_t quiet = M ? (1u << (M - 1u)) : 0u;
+  const uint32_t c_nan = inf_code | quiet | (t & ((1u << M) - 1u));
+  uint32_t c = ax >= (emin << 23) ? c_norm : c_sub;
+  c = ax > 0x7F800000u ? c_nan : c;
+  return c | ((x >> 31) << (E + M));
+}
+
+__device__ __forceinline__ uint32_t enc_f64_rne(uint64_t x, uint32_t E, uint32_t M) {
+  const uint32_t sh = 52u - M;  // >= 21: codes have at most 32 bits
+  const uint32_t bias = (1u << (E - 1u)) - 1u;
+  const uint32_t emin = 1024u - bias;
+  const uint64_t inf_code = (uint64_t)(((1u << E) - 1u) << M);
+  const uint64_t ax = x & 0x7FFFFFFFFFFFFFFFull;
+  const uint64_t t = ax >> sh;
+  const uint64_t rem = ax & ((1ull << sh) - 1ull), half = 1ull << (sh - 1u);
+  const uint64_t odd = M ? (t & 1ull) : 1ull;
+  const uint64_t up = (rem > half || (rem == half && odd)) ? 1ull : 0ull;
+  const uint64_t cn = t + up - ((uint64_t)(emin - 1u) << M);
+  const uint32_t c_norm = (uint32_t)(cn < inf_code ? cn : inf_code);
+  const uint32_t k = bias + M - 1u;  // 0 .. 1051
+  const uint32_t k1 = k < 1023u ? k : 1023u;
+  const double s1 = __builtin_bit_cast(double, (uint64_t)(k1 + 1023u) << 52);
+  const double s2 = __builtin_bit_cast(double, (uint64_t)(k - k1 + 1023u) << 52);
+  const double mag = __builtin_bit_cast(double, ax) * s1 * s2;
+  const uint32_t c_sub = ax < ((uint64_t)emin << 52) ? (uint32_t)__builtin_rint(mag) : 0u;
+  const uint32_t quiet = M ? (1u << (M - 1u)) : 0u;
+  const uint32_t c_nan = (uint32_t)inf_code | quiet | (uint32_t)(t & ((1ull << M) - 1ull));
+  uint32_t c = ax >= ((uint64_t)emin << 52) ? c_norm : c_sub;
+  c = ax > 0x7FF0000000000000ull ? c_nan : c;
+  return c | ((uint32_t)(x >> 63) << (E + M));
+}
+
 __device__ __forceinline__ uint32_t dec_f32(uint32_t c, uint32_t E, uint32_t M) {
   const uint32_t sh = 23u - M;
   const uint32_t bias = (1u << (E - 1u)) - 1u;
@@ -1052,8 +1106,10 @@ __device__ __forceinline__ uint64_t dec_f64(uint32_t c, uint32_t E, uint32_t M) 
 // user element -> code (pack)
 template <int CODEC>
 __device__ __forceinline__ uint32_t encode(uint64_t v, const Side& d) {
-  if constexpr (CODEC == CD_F32) return enc_f32((uint32_t)v, d.exp_bits, d.man_bits);
-  else if constexpr (CODEC == CD_F64) return enc_f64(v, d.exp_bits, d.man_bits);
+  if constexpr (CODEC == CD_F32)
+    return d.rne ? enc_f32_rne((uint32_t)v, d.exp_bits, d.man_bits) : enc_f32((uint32_t)v, d.exp_bits, d.man_bits);
+  else if constexpr (CODEC == CD_F64)
+    return d.rne ? enc_f64_rne(v, d.exp_bits, d.man_bits) : enc_f64(v, d.exp_bits, d.man_bits);
   else return (uint32_t)v & (d.bits >= 32u ? 0xFFFFFFFFu : ((1u << d.bits) - 1u));
 }
 

@@ -79,6 +79,10 @@ def test_descriptor_errors():
     assert err(c, F32x7, {"kind": "changetype", "stored": ["i32"] * 7, "inner": {"kind": "aos"}}) == "INVALID_ARG"
     assert err(c, ["f16"], {"kind": "changetype", "stored": ["bf16"], "inner": {"kind": "aos"}}) == "INVALID_ARG"
     assert err(c, F32x7, {"kind": "bytesplit", "inner": {"kind": "bytesplit", "inner": {"kind": "aos"}}}) == "INVALID_ARG"
+    # the rounding flag belongs to BitPackedFloatSoA only
+    assert err(c, F32x7, {"kind": "aos", "round": "rne"}) == "INVALID_ARG"
+    assert err(c, ["i32"], {"kind": "bitpack_int", "bits": 5, "round": "rne"}) == "INVALID_ARG"
+    assert c(["f32"], {"kind": "bitpack_float", "exp": 5, "man": 10, "round": "rne"}) == 1
     assert err(c, [], {"kind": "aos"}) == "INVALID_ARG"
     assert err(c, ["f32"] * 65, {"kind": "aos"}) == "INVALID_ARG"
 

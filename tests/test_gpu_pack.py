@@ -131,3 +131,28 @@ def test_bitpack_float_strided_2_32(E, M):
     comp = {"kind": "bitpack_float", "exp": E, "man": M}
     say("strided", E, M, n)
     pack_unpack(rec, {"kind": "soa_mb"}, comp, n, [bits.view(np.float32)])
+
+
+@pytest.mark.parametrize("E,M", [(5, 10), (8, 7), (8, 15), (3, 0), (4, 3), (6, 20)])
+def test_bitpack_float_rne_f32(E, M):
+    """BitPackedFloatSoA with round-to-nearest-even codes (mapping flag), from
+    AoS and from element planes on and off the 16-byte grid; values around the
+    half formats' ranges with exact ties, and the special mix."""
+    rec = ["f32"] * 2
+    comp = {"kind": "bitpack_float", "exp": E, "man": M, "round": "rne"}
+    for n, phys in ((300, PHYS[0]), (4097, PHYS[1]), (301, PHYS[2]), (1000, PHYS[4])):
+        planes = [synth.narrow_range_values(n, seed=n + f + E * 7 + M).view(np.float32) for f in range(2)]
+        say("float-rne", E, M, phys, n)
+        pack_unpack(rec, phys, comp, n, planes)
+
+
+@pytest.mark.parametrize("E,M", [(8, 15), (11, 20), (5, 10), (8, 0)])
+def test_bitpack_float_rne_f64(E, M):
+    n = 2000
+    rec = ["f64"] * 3
+    planes = [synth.narrow_range_values(n, seed=E * 100 + M + f, dtype=np.float64).view(np.float64) for f in range(2)]
+    planes.append(synth.changetype_values(n, seed=E + M)[0])
+    comp = {"kind": "bitpack_float", "exp": E, "man": M, "round": "rne"}
+    for phys in (PHYS[0], PHYS[1], PHYS[3]):
+        say("float64-rne", E, M, phys)
+        pack_unpack(rec, phys, comp, n, planes)

@@ -380,3 +380,117 @@ def test_float_encode_all_2_32(E, M):
         got = oracle.float_encode_array(bits, "f32", E, M)
         exp = closed_form_e8(bits, M) if E == 8 else closed_form_e5m10(bits)
         assert np.array_equal(got, exp)
+
+
+# ---------------------------------------------------------------- BitPackedFloat, round to nearest even
+# Sec. 3 only asks that the mantissa be "preserved as best as possible"; the
+# mapping truncates by default and rounds to nearest, ties to even, when its
+# round flag asks for it.  Ties compare the significand's last bit, which for
+# M = 0 is the (always set) hidden bit: there a tie rounds away from zero.
+
+def encode_rne_reference(x, E, M):
+    """Nearest representable value (independent exact-rational definition)."""
+    f = float(x)
+    sign = 1 if np.signbit(f) else 0
+    ax = abs(Fraction(f))
+    bias = (1 << (E - 1)) - 1
+    inf_code = ((1 << E) - 1) << M
+    top = Fraction(2) ** (bias + 1)  # the next value after the largest finite one
+    if ax >= top:
+        return inf_code | (sign << (E + M))
+    lo, hi = 0, inf_code - 1
+    while lo < hi:  # largest code whose value is <= ax
+        mid = (lo + hi + 1) // 2
+        if decode_exact(mid, E, M) <= ax:
+            lo = mid
+        else:
+            hi = mid - 1
+    lo_v = decode_exact(lo, E, M)
+    hi_v = decode_exact(lo + 1, E, M) if lo + 1 < inf_code else top
+    if ax - lo_v < hi_v - ax:
+        c = lo
+    elif ax - lo_v > hi_v - ax:
+        c = lo + 1
+    else:
+        even = (lo & 1) == 0 if M >= 1 else lo == 0
+        c = lo if even else lo + 1
+    return c | (sign << (E + M))
+
+
+def tie_values(E, M, rng, k=40):
+    """f32 values exactly halfway between two neighbouring codes."""
+    bias = (1 << (E - 1)) - 1
+    out = []
+    for c in rng.integers(0, ((1 << E) - 1) << M, k):
+        c = int(c)
+        a = decode_exact(c, E, M)
+        b = decode_exact(c + 1, E, M) if c + 1 < ((1 << E) - 1) << M else Fraction(2) ** (bias + 1)
+        mid = (a + b) / 2
+        f = np.float32(float(mid))
+        if np.isfinite(f) and Fraction(float(f)) == mid:
+            out += [float(f), -float(f)]
+    return out
+
+
+@pytest.mark.parametrize("E", list(range(2, 9)))
+def test_float_encode_rne_brute_force(E):
+    rng = np.random.default_rng(100 + E)
+    for M in (0, 1, 2, 3, 7, 10, 15, 23):
+        for v in probe_values(E, M, rng) + tie_values(E, M, rng):
+            bits = int(np.float32(v).view(np.uint32))
+            got = int(oracle.float_encode_array(np.array([bits], np.uint32).view(np.float32), "f32", E, M, rne=True)[0])
+            assert got == encode_rne_reference(np.float32(v), E, M), (E, M, hex(bits))
+
+
+def test_float_encode_rne_e5m10_equals_numpy_float16():
+    x = strided_f32(stride=263).view(np.float32)
+    x = x[~np.isnan(x)]
+    got = oracle.float_encode_array(x, "f32", 5, 10, rne=True)
+    with np.errstate(over="ignore"):
+        ref = x.astype(np.float16).view(np.uint16)
+    assert np.array_equal(got.astype(np.uint16), ref)
+
+
+def test_float_encode_rne_e8m7_equals_torch_bfloat16():
+    torch = pytest.importorskip("torch")
+    x = strided_f32(stride=271).view(np.float32)
+    x = x[~np.isnan(x)]
+    got = oracle.float_encode_array(x, "f32", 8, 7, rne=True)
+    ref = torch.from_numpy(x.copy()).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(got.astype(np.uint16), ref)
+
+
+def test_float_encode_rne_from_f64_e8m23_equals_numpy_float32():
+    rng = np.random.default_rng(5)
+    bits = rng.integers(0, 2 ** 64, 400000, dtype=np.uint64, endpoint=False)
+    x = bits.view(np.float64)
+    x = np.concatenate([x[~np.isnan(x)], rng.standard_normal(100000) * 10.0 ** rng.integers(-45, 39, 100000)])
+    got = oracle.float_encode_array(x, "f64", 8, 23, rne=True)
+    with np.errstate(over="ignore"):
+        ref = x.astype(np.float32).view(np.uint32)
+    assert np.array_equal(got.astype(np.uint32), ref)
+
+
+def test_float_encode_rne_nan_rule_equals_truncation():
+    rng = np.random.default_rng(6)
+    nan = (rng.integers(0, 2, 5000, dtype=np.uint32) << np.uint32(31)) | np.uint32(0x7F800000) | \
+        rng.integers(1, 1 << 23, 5000, dtype=np.uint32)
+    x = nan.view(np.float32)
+    for E, M in ((5, 10), (8, 7), (3, 0), (6, 12)):
+        assert np.array_equal(oracle.float_encode_array(x, "f32", E, M, rne=True),
+                              oracle.float_encode_array(x, "f32", E, M))
+
+
+def test_float_rne_view_copy_uses_the_flag():
+    rng = np.random.default_rng(7)
+    n = 3000
+    x = rng.standard_normal(n).astype(np.float32) * np.float32(1000)
+    spec = {"kind": "bitpack_float", "exp": 5, "man": 10, "round": "rne"}
+    blobs = oracle.store_planes(["f32"], {"kind": "soa_mb"}, [x])
+    packed = oracle.copy(["f32"], {"kind": "soa_mb"}, blobs, spec, n)
+    codes = oracle.float_encode_array(x, "f32", 5, 10, rne=True)
+    stream = np.zeros(4 * ((n * 16 + 31) // 32), np.uint8)
+    stream[: 2 * n] = codes.astype(np.uint16).view(np.uint8)
+    assert np.array_equal(packed[0], stream)
+    trunc = oracle.copy(["f32"], {"kind": "soa_mb"}, blobs, {"kind": "bitpack_float", "exp": 5, "man": 10}, n)
+    assert not np.array_equal(packed[0], trunc[0])
