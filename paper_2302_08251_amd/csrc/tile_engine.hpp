@@ -15,6 +15,7 @@
 // the mapping uses, so an access outside the blob is dropped by hardware.
 // Per-lane offsets are 32-bit; only the per-segment scalar base is 64-bit.
 #pragma once
+#include <type_traits>
 #include <hip/hip_runtime.h>
 
 #include "internal.hpp"
@@ -906,28 +907,34 @@ __device__ __forceinline__ uint64_t cvt_f32_f64(uint32_t x) {
 // significand that still carries its hidden bit lets a rounding carry move
 // into the exponent by itself.  Codes at or past the Inf code become Inf.
 // A NaN keeps its sign and top MD payload bits and gets the quiet bit.
+// Both work in 32-bit words when source and target fit in them (W).
 template <int ES, int MS, int ED, int MD>
-__device__ __forceinline__ uint64_t narrow_rne(uint64_t x) {
+using ConvWord = typename std::conditional<(ES + MS < 32 && ED + MD < 32), uint32_t, uint64_t>::type;
+
+template <int ES, int MS, int ED, int MD>
+__device__ __forceinline__ uint64_t narrow_rne(uint64_t x64) {
+  using W = ConvWord<ES, MS, ED, MD>;
+  const W x = (W)x64;
   constexpr int emax_s = (1 << ES) - 1, emax_d = (1 << ED) - 1;
   constexpr int bias_s = (1 << (ES - 1)) - 1, bias_d = (1 << (ED - 1)) - 1;
-  const uint64_t sign = (x >> (ES + MS)) & 1ull;
-  const uint64_t m = x & ((1ull << MS) - 1ull);
-  const int es = (int)((x >> MS) & (uint64_t)emax_s);
-  uint64_t code;
+  const W sign = (x >> (ES + MS)) & (W)1;
+  const W m = x & (((W)1 << MS) - (W)1);
+  const int es = (int)((x >> MS) & (W)emax_s);
+  W code;
   if (es == emax_s) {
-    code = ((uint64_t)emax_d << MD) | (m ? ((m >> (MS - MD)) | (1ull << (MD - 1))) : 0ull);
+    code = ((W)emax_d << MD) | (m ? ((m >> (MS - MD)) | ((W)1 << (MD - 1))) : (W)0);
   } else {
-    const uint64_t sig = es ? (m | (1ull << MS)) : m;
+    const W sig = es ? (m | ((W)1 << MS)) : m;
     const int ed = (es ? es : 1) - bias_s + bias_d;  // target exponent field of the hidden-bit position
     const int sh = MS - MD + (ed < 1 ? 1 - ed : 0);  // >= 1: the formats narrow
-    uint64_t q = 0;
+    W q = 0;
     if (sh <= MS + 1) {  // otherwise the value is below half the smallest subnormal
       q = sig >> sh;
-      const uint64_t rem = sig & ((1ull << sh) - 1ull), half = 1ull << (sh - 1);
-      q += (rem > half || (rem == half && (q & 1ull))) ? 1ull : 0ull;
+      const W rem = sig & (((W)1 << sh) - (W)1), half = (W)1 << (sh - 1);
+      q += (rem > half || (rem == half && (q & (W)1))) ? (W)1 : (W)0;
     }
-    code = ed >= 1 ? ((uint64_t)(ed - 1) << MD) + q : q;
-    const uint64_t inf = (uint64_t)emax_d << MD;
+    code = ed >= 1 ? ((W)(ed - 1) << MD) + q : q;
+    const W inf = (W)emax_d << MD;
     code = code >= inf ? inf : code;
   }
   return code | (sign << (ED + MD));
@@ -937,26 +944,28 @@ __device__ __forceinline__ uint64_t narrow_rne(uint64_t x) {
 // target exponent range is wider (a subnormal when it is the same); a NaN's
 // payload moves up and the quiet bit is set.
 template <int ES, int MS, int ED, int MD>
-__device__ __forceinline__ uint64_t widen(uint64_t x) {
+__device__ __forceinline__ uint64_t widen(uint64_t x64) {
+  using W = ConvWord<ES, MS, ED, MD>;
+  const W x = (W)x64;
   constexpr int emax_s = (1 << ES) - 1, emax_d = (1 << ED) - 1;
   constexpr int bias_s = (1 << (ES - 1)) - 1, bias_d = (1 << (ED - 1)) - 1;
-  const uint64_t sign = (x >> (ES + MS)) & 1ull;
-  const uint64_t m = x & ((1ull << MS) - 1ull);
-  const int es = (int)((x >> MS) & (uint64_t)emax_s);
-  uint64_t code;
+  const W sign = (x >> (ES + MS)) & (W)1;
+  const W m = x & (((W)1 << MS) - (W)1);
+  const int es = (int)((x >> MS) & (W)emax_s);
+  W code;
   if (es == emax_s) {
-    code = ((uint64_t)emax_d << MD) | (m << (MD - MS)) | (m ? (1ull << (MD - 1)) : 0ull);
+    code = ((W)emax_d << MD) | (m << (MD - MS)) | (m ? ((W)1 << (MD - 1)) : (W)0);
   } else if (es == 0) {
     if (m == 0) {
       code = 0;
     } else if constexpr (ED == ES) {  // same exponent range: still a subnormal
       code = m << (MD - MS);
     } else {  // m * 2^(1 - bias_s - MS), a normal of the wider range
-      const int p = 63 - __builtin_clzll(m);
-      code = ((uint64_t)(p + 1 - bias_s - MS + bias_d) << MD) | ((m ^ (1ull << p)) << (MD - p));
+      const int p = 63 - __builtin_clzll((uint64_t)m);
+      code = ((W)(p + 1 - bias_s - MS + bias_d) << MD) | ((m ^ ((W)1 << p)) << (MD - p));
     }
   } else {
-    code = ((uint64_t)(es - bias_s + bias_d) << MD) | (m << (MD - MS));
+    code = ((W)(es - bias_s + bias_d) << MD) | (m << (MD - MS));
   }
   return code | (sign << (ED + MD));
 }
@@ -1174,9 +1183,63 @@ __device__ __forceinline__ uint64_t convert(uint64_t v) {
   else return widen<8, 7, 11, 52>(v);
 }
 
+// Element planes on both sides, runs on the 16-byte grid: a lane converts the
+// 16 / ES_DST values of one destination chunk from contiguous source
+// elements (wide LDS reads) and stores the chunk whole.
+template <int CONV>
+__device__ __forceinline__ void store_conv_planar(const Side& s, const Side& d, uint64_t i0, uint32_t nt,
+                                                  const uint8_t* lds, uint32_t f) {
+  constexpr int ESS = ConvInfo<CONV>::ES_SRC, ESD = ConvInfo<CONV>::ES_DST;
+  constexpr int V = 16 / ESD;         // values per destination chunk
+  constexpr int NB = V * ESS;         // source bytes per chunk: 4 .. 64
+  const uint32_t chunks = (nt + V - 1u) / V;
+  const uint64_t start = seg_start(d, f, i0);
+  const auto rs = make_rsrc((const uint8_t*)seg_blob(d, f) + start, d.blob_size - start);
+  const uint8_t* plane = lds + f * s.lds_stride;
+  for (uint32_t c = threadIdx.x; c < chunks; c += blockDim.x) {
+    const uint32_t r = c * V;
+    uint32_t raw[NB / 4];
+    const uint8_t* p = plane + r * ESS;
+    if constexpr (NB >= 16) {
+#pragma unroll
+      for (int q = 0; q < NB / 16; ++q) {
+        const u32x4 x = *(const u32x4*)(p + 16 * q);
+        raw[4 * q] = x.x;
+        raw[4 * q + 1] = x.y;
+        raw[4 * q + 2] = x.z;
+        raw[4 * q + 3] = x.w;
+      }
+    } else if constexpr (NB == 8) {
+      const u32x2 x = *(const u32x2*)p;
+      raw[0] = x.x;
+      raw[1] = x.y;
+    } else {
+      raw[0] = *(const uint32_t*)p;
+    }
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      uint64_t e;
+      if constexpr (ESS == 8) e = (uint64_t)raw[2 * k] | ((uint64_t)raw[2 * k + 1] << 32);
+      else if constexpr (ESS == 4) e = raw[k];
+      else e = (raw[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+      put_unit<ESD>(w, k, convert<CONV>(e));
+    }
+    const uint32_t valid = nt - r >= (uint32_t)V ? (1u << V) - 1u : (1u << (nt - r)) - 1u;
+    store_chunk<ESD>(rs, 16u * c, w, valid, (1u << V) - 1u);
+  }
+}
+
 template <int CONV, int U, int DL, int SL>
 __device__ __forceinline__ void store_conv(const Side& s, const Side& d, uint64_t i0, uint32_t nt,
                                            const uint8_t* lds) {
+  if constexpr (DL == LY_PLANAR && SL == LY_PLANAR && U == ConvInfo<CONV>::ES_DST) {
+    constexpr uint32_t ESS = ConvInfo<CONV>::ES_SRC, ESD = ConvInfo<CONV>::ES_DST;
+    if (s.cs == ESS && (s.mb || ((s.n * ESS) & 15u) == 0u) && (d.mb || ((d.n * ESD) & 15u) == 0u)) {
+      for (uint32_t f = 0; f < d.ncols; ++f) store_conv_planar<CONV>(s, d, i0, nt, lds, f);
+      return;
+    }
+  }
   constexpr int NU = 16 / U;
   constexpr uint32_t FULL = (1u << NU) - 1u;
   constexpr int ESS = ConvInfo<CONV>::ES_SRC, ESD = ConvInfo<CONV>::ES_DST;
