@@ -1305,7 +1305,10 @@ __device__ __forceinline__ void store_pack(const Side& s, const Side& d, uint64_
           const uint32_t r = 4u * q;
           uint32_t c[4];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) c[k] = r + k < nt ? encode<CODEC>(v[k], d) : 0u;
+          for (int k = 0; k < 4; ++k) {  // branch-free: values past the tile give code 0
+            const uint32_t keep = 0u - (uint32_t)(r + k < nt);
+            c[k] = encode<CODEC>(v[k], d) & keep;
+          }
           const uint32_t bit = r * B;
           if (B <= 8u) {
             or_bits(wf, bit, c[0] | (c[1] << B) | (c[2] << (2u * B)) | (c[3] << (3u * B)), 4u * B);
