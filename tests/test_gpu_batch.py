@@ -105,3 +105,31 @@ def test_batch_every_tile_choice_matches_oracle(tmp_path, code, grid):
     torch.cuda.synchronize()
     check(views, "tile code %d grid %d" % (code, grid))
     b.close()
+
+
+def test_batch_mixed_record_types_matches_oracle():
+    """One launch over views of different leaf sizes (f64, f32, i16, u8 records)
+    and mappings, Bytesplit included; every view equals the oracle's copy."""
+    torch = pytest.importorskip("torch")
+    recs = [["f64"] * 3, ["f32"] * 7, ["i16", "u16", "i16"], ["u8"] * 5]
+    maps = [{"kind": "aos"}, {"kind": "soa_sb"}, {"kind": "soa_mb"}, {"kind": "aosoa", "lanes": 32},
+            {"kind": "bytesplit", "inner": {"kind": "soa_sb"}}, {"kind": "bytesplit", "inner": {"kind": "aos"}}]
+    rng = np.random.default_rng(11)
+    views = []
+    for k in range(48):
+        rec = recs[k % len(recs)]
+        a, b = rng.choice(len(maps), 2, replace=False)
+        n = int(rng.integers(1, 9000))
+        planes = bits_planes(n, rec, seed=500 + k)
+        src_host = oracle.store_planes(rec, maps[a], planes, fill=0x5A)
+        exp = oracle.copy(rec, maps[a], src_host, maps[b], n, fill=0xA5)
+        views.append((gpu_view(rec, maps[a], n, src_host), gpu_view(rec, maps[b], n, fill=0xA5), exp,
+                      (str(rec[0]), maps[a]["kind"], maps[b]["kind"], n)))
+    batch = lm.Batch([v[0] for v in views], [v[1] for v in views])
+    reset(views)
+    batch.launch()
+    torch.cuda.synchronize()
+    check(views, "mixed records")
+    batch.launch_per_view()
+    check(views, "mixed records, per view")
+    batch.close()
