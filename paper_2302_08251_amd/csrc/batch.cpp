@@ -26,6 +26,7 @@ struct llama_batch {
   double tune_seconds = 0;
   BatchItem* d_items = nullptr;
   uint32_t* d_prefix = nullptr;
+  uint32_t* d_tile_view = nullptr;  // view of every tile
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -45,8 +46,10 @@ void release_device(llama_batch* b) {
   b->graph = nullptr;
   if (b->d_items) (void)hipFree(b->d_items);
   if (b->d_prefix) (void)hipFree(b->d_prefix);
+  if (b->d_tile_view) (void)hipFree(b->d_tile_view);
   b->d_items = nullptr;
   b->d_prefix = nullptr;
+  b->d_tile_view = nullptr;
 }
 
 // Work list for tile size T: per-view plans, tile prefix sums, max LDS.  The
@@ -118,6 +121,14 @@ llama_status upload(llama_batch* b, uint32_t T) {
   if ((e = hipMemcpy(b->d_prefix, prefix.data(), prefix.size() * sizeof(uint32_t), hipMemcpyHostToDevice)) !=
       hipSuccess)
     return hip_fail(e, "hipMemcpy");
+  std::vector<uint32_t> tv(prefix.back());
+  for (size_t k = 0; k + 1 < prefix.size(); ++k)
+    std::fill(tv.begin() + prefix[k], tv.begin() + prefix[k + 1], (uint32_t)k);
+  if (!tv.empty()) {
+    if ((e = hipMalloc(&b->d_tile_view, tv.size() * sizeof(uint32_t))) != hipSuccess) return hip_fail(e, "hipMalloc");
+    if ((e = hipMemcpy(b->d_tile_view, tv.data(), tv.size() * sizeof(uint32_t), hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "hipMemcpy");
+  }
   b->tile = T;
   b->lds = lds;
   b->total_tiles = prefix.back();
@@ -132,7 +143,7 @@ llama_status capture(llama_batch* b) {
   b->graph = nullptr;
   if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
     return hip_fail(e, "hipStreamBeginCapture");
-  hipError_t le = launch_batch(b->d_items, b->d_prefix, (uint32_t)b->total_tiles, (uint32_t)b->srcs.size(), b->grid, b->lds, b->cap);
+  hipError_t le = launch_batch(b->d_items, b->d_prefix, b->d_tile_view, (uint32_t)b->total_tiles, (uint32_t)b->srcs.size(), b->grid, b->lds, b->cap);
   e = hipStreamEndCapture(b->cap, &b->graph);
   if (le != hipSuccess) return hip_fail(le, "batched launch");
   if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
@@ -257,7 +268,7 @@ llama_status autotune(llama_batch* b, uint64_t granule, uint32_t& bestT, uint32_
           1, std::min<uint64_t>(mult ? (uint64_t)cus * mult : b->total_tiles, b->total_tiles));
       hipError_t le = hipSuccess;
       auto run = [&]() {
-        hipError_t e = launch_batch(b->d_items, b->d_prefix, (uint32_t)b->total_tiles, (uint32_t)b->srcs.size(), G, b->lds, b->cap);
+        hipError_t e = launch_batch(b->d_items, b->d_prefix, b->d_tile_view, (uint32_t)b->total_tiles, (uint32_t)b->srcs.size(), G, b->lds, b->cap);
         if (e != hipSuccess) le = e;
       };
       run();

@@ -13,7 +13,8 @@ struct BatchItem {
   uint32_t pad[2];
 };
 
-hipError_t launch_batch(const BatchItem* items, const uint32_t* prefix, uint32_t total_tiles, uint32_t n_views,
-                        uint32_t grid, uint32_t lds, hipStream_t st);
+// tile_view: view index of every tile (total_tiles entries), or null
+hipError_t launch_batch(const BatchItem* items, const uint32_t* prefix, const uint32_t* tile_view,
+                        uint32_t total_tiles, uint32_t n_views, uint32_t grid, uint32_t lds, hipStream_t st);
 
 }  // namespace lm

@@ -12,14 +12,19 @@
 namespace lm {
 
 __global__ __launch_bounds__(kThreads) void k_batch(const BatchItem* __restrict__ items,
-                                                   const uint32_t* __restrict__ prefix, uint32_t total_tiles,
+                                                   const uint32_t* __restrict__ prefix,
+                                                   const uint32_t* __restrict__ tile_view, uint32_t total_tiles,
                                                    uint32_t n_views) {
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   uint32_t v = 0;
   for (uint32_t t = blockIdx.x; t < total_tiles; t += gridDim.x) {
-    // view holding tile t: prefix[v] <= t < prefix[v + 1].  Tiles are visited
-    // in increasing order, so gallop forward from the last view, then bisect.
-    if (prefix[v + 1] <= t) {
+    // view holding tile t: prefix[v] <= t < prefix[v + 1].  With one
+    // workgroup per tile the host's tile -> view table answers in one load;
+    // a persistent workgroup visits its tiles in increasing order and
+    // gallops forward from the last view, then bisects.
+    if (tile_view) {
+      v = tile_view[t];
+    } else if (prefix[v + 1] <= t) {
       uint32_t step = 1, lo = v + 1, hi = v + 1;
       while (hi < n_views && prefix[hi + 1] <= t) {
         lo = hi + 1;
@@ -48,9 +53,11 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchItem* __restrict_
   }
 }
 
-hipError_t launch_batch(const BatchItem* items, const uint32_t* prefix, uint32_t total_tiles, uint32_t n_views,
-                        uint32_t grid, uint32_t lds, hipStream_t st) {
-  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kThreads), lds, st, items, prefix, total_tiles, n_views);
+hipError_t launch_batch(const BatchItem* items, const uint32_t* prefix, const uint32_t* tile_view,
+                        uint32_t total_tiles, uint32_t n_views, uint32_t grid, uint32_t lds, hipStream_t st) {
+  // the table is used when every workgroup takes a single tile
+  const uint32_t* tv = grid >= total_tiles ? tile_view : nullptr;
+  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kThreads), lds, st, items, prefix, tv, total_tiles, n_views);
   return hipGetLastError();
 }
 
