@@ -72,6 +72,44 @@ def test_cfg2_single_view_all_pairs_full_size():
         dst.close()
 
 
+def test_cfg2_misaligned_record_count_full_size():
+    """N = 64 Mi - 13: single-blob planes start off every alignment grid, so
+    the split into byte planes writes through shifted windows and the merges
+    and column runs read misaligned planes.  Every pair that touches a
+    single-blob side, sampled bytes against the oracle's locations plus the
+    round trip."""
+    t = torch()
+    n = (64 << 20) - 13
+    planes = synth.particles(n, 1, dtype=np.float32)
+    mb = lm.View(F32x7, CFG2["soa_mb"], [n], index_type="i32",
+                 blobs=[t.from_numpy(p.view(np.uint8)).cuda() for p in planes])
+    back = lm.View(F32x7, CFG2["soa_mb"], [n], index_type="i32")
+    i, f, k = sample_ifk(n, 7, 4, 300000, seed=2)
+    want = np.empty(len(i), np.uint8)
+    for ff in range(7):
+        sel = f == ff
+        want[sel] = planes[ff].view(np.uint8)[4 * i[sel].astype(np.int64) + k[sel]]
+    pairs = [("aos", "bytesplit"), ("soa_mb", "bytesplit"), ("soa_sb", "bytesplit"), ("aosoa32", "bytesplit"),
+             ("bytesplit", "aos"), ("bytesplit", "soa_sb"), ("bytesplit", "bytesplit"), ("aos", "soa_sb"),
+             ("soa_sb", "aosoa64"), ("soa_sb", "soa_mb")]
+    views = {}
+    for a, b in pairs:
+        for key in (a, b):
+            if key not in views:
+                views[key] = lm.View(F32x7, CFG2[key], [n], index_type="i32")
+                lm.llama_copy(mb, views[key])
+        dst = lm.View(F32x7, CFG2[b], [n], index_type="i32")
+        say("cfg2 misaligned", a, "->", b)
+        lm.llama_copy(views[a], dst)
+        blob, off = oracle.locate_many(F32x7, CFG2[b], n, i, f, k)
+        assert np.array_equal(gather(dst, blob, off), want), "%s -> %s sampled bytes differ" % (a, b)
+        lm.llama_copy(dst, back)
+        t.cuda.synchronize()
+        for ff in range(7):
+            assert t.equal(back.blobs[ff][: 4 * n], mb.blobs[ff][: 4 * n]), (a, b, ff)
+        dst.close()
+
+
 def extract_codes(blob_u8, idx, B):
     """codes of sampled values from a downloaded bit stream (LSB first)"""
     words = blob_u8.view(np.uint32).astype(np.uint64)
