@@ -121,9 +121,12 @@ llama_status upload(llama_batch* b, uint32_t T) {
   if ((e = hipMemcpy(b->d_prefix, prefix.data(), prefix.size() * sizeof(uint32_t), hipMemcpyHostToDevice)) !=
       hipSuccess)
     return hip_fail(e, "hipMemcpy");
-  std::vector<uint32_t> tv(prefix.back());
-  for (size_t k = 0; k + 1 < prefix.size(); ++k)
-    std::fill(tv.begin() + prefix[k], tv.begin() + prefix[k + 1], (uint32_t)k);
+  // tile -> view table (4 bytes per tile) for one-workgroup-per-tile
+  // launches; very large batches (over 64 Mi tiles) search instead
+  std::vector<uint32_t> tv(prefix.back() <= (64u << 20) ? prefix.back() : 0u);
+  if (!tv.empty())
+    for (size_t k = 0; k + 1 < prefix.size(); ++k)
+      std::fill(tv.begin() + prefix[k], tv.begin() + prefix[k + 1], (uint32_t)k);
   if (!tv.empty()) {
     if ((e = hipMalloc(&b->d_tile_view, tv.size() * sizeof(uint32_t))) != hipSuccess) return hip_fail(e, "hipMalloc");
     if ((e = hipMemcpy(b->d_tile_view, tv.data(), tv.size() * sizeof(uint32_t), hipMemcpyHostToDevice)) != hipSuccess)
