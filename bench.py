@@ -363,10 +363,32 @@ def cpu_baseline(n_sample):
                 break
     except OSError:
         pass
+    # further oracle figures on bounded samples: one thread on one pair, the
+    # B = 12 int pack, and the FP64 n-body (the GPU rows' workloads)
+    n1 = min(n_sample, 1 << 19)
+    b1 = oracle.store_planes(F32x7, LAYOUTS["AoS"], [p[:n1] for p in planes], threads=threads)
+    t0 = time.perf_counter()
+    oracle.copy(F32x7, LAYOUTS["AoS"], b1, LAYOUTS["SoA-MB"], n1, threads=1)
+    one_thread = 2 * n1 * 28 / (time.perf_counter() - t0) / 1e9
+    n_int = 16 << 20
+    vals = [synth.int_values(n_int, 12, 0)]
+    ib = oracle.store_planes(["i32"], {"kind": "soa_mb"}, vals, threads=threads)
+    t0 = time.perf_counter()
+    oracle.copy(["i32"], {"kind": "soa_mb"}, ib, {"kind": "bitpack_int", "bits": 12}, n_int, threads=threads)
+    pack12 = (4 * n_int + n_int * 12 // 8) / (time.perf_counter() - t0) / 1e9
+    n_nb = 16384
+    pl = synth.particles(n_nb, 0, dtype=np.float64)
+    pos, vel = np.stack(pl[0:3], 1), np.stack(pl[3:6], 1)
+    t0 = time.perf_counter()
+    oracle.nbody(pos, vel, pl[6], 1, 1e-4, 0.01, threads=threads)
+    nb_ips = float(n_nb) * n_nb / (time.perf_counter() - t0)
     return {"value": tot_bytes / tot_s / 1e9, "unit": "GB/s", "cores": threads, "kind": "oracle",
             "sample": "first %d of the 64Mi records, all 36 ordered pairs, element-by-element oracle "
                       "copy (OpenMP over record blocks); cpu: %s" % (n_sample, model),
-            "seconds": tot_s}
+            "seconds": tot_s,
+            "also": {"copy_AoS_to_SoA-MB_1_thread_gbs": one_thread, "copy_1_thread_records": n1,
+                     "int_pack_B12_gbs": pack12, "int_pack_B12_values": n_int,
+                     "nbody_fp64_interactions_per_s": nb_ips, "nbody_fp64_n": n_nb}}
 
 
 def main():
