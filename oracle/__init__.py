@@ -21,7 +21,7 @@ from . import build as _build
 _TYPES = {"f32": 0, "f64": 1, "i8": 2, "u8": 3, "i16": 4, "u16": 5, "i32": 6, "u32": 7,
           "i64": 8, "u64": 9, "f16": 10, "bf16": 11}
 _KINDS = {"aos": 0, "soa_sb": 1, "soa_mb": 2, "aosoa": 3, "bytesplit": 4, "changetype": 5,
-          "bitpack_int": 6, "bitpack_float": 7}
+          "bitpack_int": 6, "bitpack_float": 7, "null": 8, "split": 9}
 TYPE_SIZE = {"f32": 4, "f64": 8, "i8": 1, "u8": 1, "i16": 2, "u16": 2, "i32": 4, "u32": 4,
              "i64": 8, "u64": 8, "f16": 2, "bf16": 2}
 
@@ -122,6 +122,11 @@ def _map(spec, keep):
         m.stored_types = arr
     if "inner" in spec:
         m.inner = C.pointer(_map(spec["inner"], keep))
+    if spec["kind"] == "split":  # {"kind": "split", "at": k, "parts": [first, second]}
+        m.lanes = spec["at"]
+        parts = (_Map * 2)(_map(spec["parts"][0], keep), _map(spec["parts"][1], keep))
+        keep.objs.append(parts)
+        m.inner = C.cast(parts, C.POINTER(_Map))
     keep.objs.append(m)
     return m
 

@@ -277,6 +277,19 @@ static uint32_t code_bits(const orc_map* m) {
 /* Mapping: where does byte k of leaf f of record i live?                    */
 /* ------------------------------------------------------------------------ */
 
+/* Split (Sec. 3): fields [0, k) form the record of part 0 (mapping
+ * inner[0]), fields [k, F) that of part 1 (inner[1]); the view's blobs are
+ * part 0's followed by part 1's.  Null (Sec. 3) has no blobs: a load gives
+ * zero, a store is dropped. */
+static orc_rec split_part(const orc_rec* rec, const orc_map* m, int part) {
+  orc_rec r;
+  r.nf = part ? rec->nf - m->lanes : m->lanes;
+  r.types = part ? rec->types + m->lanes : rec->types;
+  return r;
+}
+
+EXPORT uint32_t orc_blob_count(const orc_rec* rec, const orc_map* m);
+
 EXPORT int orc_locate(const orc_rec* rec, const orc_map* m, uint64_t n, uint64_t i, uint32_t f,
                       uint32_t k, uint32_t* blob, uint64_t* off) {
   const uint64_t s = orc_type_size(rec->types[f]);
@@ -306,8 +319,17 @@ EXPORT int orc_locate(const orc_rec* rec, const orc_map* m, uint64_t n, uint64_t
       orc_rec br = byte_record(rec);
       return orc_locate(&br, m->inner, n, i, (uint32_t)(packed_offset(rec, f) + k), 0, blob, off);
     }
+    case ORC_SPLIT: {
+      const int part = f >= m->lanes;
+      orc_rec pr = split_part(rec, m, part);
+      if (!part) return orc_locate(&pr, &m->inner[0], n, i, f, k, blob, off);
+      orc_rec p0 = split_part(rec, m, 0);
+      int rc = orc_locate(&pr, &m->inner[1], n, i, f - m->lanes, k, blob, off);
+      *blob += orc_blob_count(&p0, &m->inner[0]);
+      return rc;
+    }
   }
-  return -1;
+  return -1;  /* Null and the computed mappings have no byte locations */
 }
 
 EXPORT uint32_t orc_blob_count(const orc_rec* rec, const orc_map* m) {
@@ -316,6 +338,11 @@ EXPORT uint32_t orc_blob_count(const orc_rec* rec, const orc_map* m) {
     case ORC_SOA_MB: case ORC_BITPACK_INT: case ORC_BITPACK_FLOAT: return rec->nf;
     case ORC_BYTESPLIT: { orc_rec br = byte_record(rec); return orc_blob_count(&br, m->inner); }
     case ORC_CHANGETYPE: { orc_rec sr = stored_record(rec, m); return orc_blob_count(&sr, m->inner); }
+    case ORC_NULL: return 0;
+    case ORC_SPLIT: {
+      orc_rec p0 = split_part(rec, m, 0), p1 = split_part(rec, m, 1);
+      return orc_blob_count(&p0, &m->inner[0]) + orc_blob_count(&p1, &m->inner[1]);
+    }
   }
   return 0;
 }
@@ -330,6 +357,12 @@ EXPORT uint64_t orc_blob_size(const orc_rec* rec, const orc_map* m, uint64_t n, 
     case ORC_CHANGETYPE: { orc_rec sr = stored_record(rec, m); return orc_blob_size(&sr, m->inner, n, b); }
     case ORC_BITPACK_INT:
     case ORC_BITPACK_FLOAT: return 4 * ((n * code_bits(m) + 31) / 32);
+    case ORC_NULL: return 0;
+    case ORC_SPLIT: {
+      orc_rec p0 = split_part(rec, m, 0), p1 = split_part(rec, m, 1);
+      const uint32_t c0 = orc_blob_count(&p0, &m->inner[0]);
+      return b < c0 ? orc_blob_size(&p0, &m->inner[0], n, b) : orc_blob_size(&p1, &m->inner[1], n, b - c0);
+    }
   }
   return 0;
 }
@@ -391,6 +424,13 @@ EXPORT uint64_t orc_load(const orc_rec* rec, const orc_map* m, uint64_t n, uint8
       uint64_t c = stream_get(blobs[f], i * B, B);
       return orc_float_decode(c, t, m->exp_bits, m->man_bits);
     }
+    case ORC_NULL: return 0;
+    case ORC_SPLIT: {
+      orc_rec p0 = split_part(rec, m, 0);
+      if (f < m->lanes) return orc_load(&p0, &m->inner[0], n, blobs, i, f);
+      orc_rec p1 = split_part(rec, m, 1);
+      return orc_load(&p1, &m->inner[1], n, blobs + orc_blob_count(&p0, &m->inner[0]), i, f - m->lanes);
+    }
   }
   return 0;
 }
@@ -422,6 +462,17 @@ EXPORT void orc_store(const orc_rec* rec, const orc_map* m, uint64_t n, uint8_t*
                               : orc_float_encode(v, t, m->exp_bits, m->man_bits));
       return;
     }
+    case ORC_NULL: return;
+    case ORC_SPLIT: {
+      orc_rec p0 = split_part(rec, m, 0);
+      if (f < m->lanes) {
+        orc_store(&p0, &m->inner[0], n, blobs, i, f, v);
+      } else {
+        orc_rec p1 = split_part(rec, m, 1);
+        orc_store(&p1, &m->inner[1], n, blobs + orc_blob_count(&p0, &m->inner[0]), i, f - m->lanes, v);
+      }
+      return;
+    }
   }
 }
 
@@ -431,6 +482,23 @@ EXPORT void orc_store(const orc_rec* rec, const orc_map* m, uint64_t n, uint8_t*
 
 static int is_bitpacked(const orc_map* m) {
   return m->kind == ORC_BITPACK_INT || m->kind == ORC_BITPACK_FLOAT;
+}
+
+/* the stream bits past the last value up to the word end are zero (also in
+ * the parts of a Split) */
+static void clear_stream_tails(const orc_rec* rec, const orc_map* m, uint8_t* const* blobs, uint64_t n) {
+  if (m->kind == ORC_SPLIT) {
+    orc_rec p0 = split_part(rec, m, 0), p1 = split_part(rec, m, 1);
+    clear_stream_tails(&p0, &m->inner[0], blobs, n);
+    clear_stream_tails(&p1, &m->inner[1], blobs + orc_blob_count(&p0, &m->inner[0]), n);
+    return;
+  }
+  if (!is_bitpacked(m)) return;
+  const uint32_t B = code_bits(m);
+  for (uint32_t f = 0; f < rec->nf; ++f) {
+    const uint64_t end = 8 * orc_blob_size(rec, m, n, f);
+    for (uint64_t q = n * B; q < end; ++q) blobs[f][q >> 3] &= (uint8_t)~(1u << (q & 7));
+  }
 }
 
 EXPORT int orc_copy(const orc_rec* rec, const orc_map* src, uint8_t* const* sblobs,
@@ -449,14 +517,7 @@ EXPORT int orc_copy(const orc_rec* rec, const orc_map* src, uint8_t* const* sblo
       for (uint32_t f = 0; f < rec->nf; ++f)
         orc_store(rec, dst, n, dblobs, i, f, orc_load(rec, src, n, sblobs, i, f));
   }
-  if (is_bitpacked(dst)) {
-    /* the stream bits past the last value up to the word end are zero */
-    uint32_t B = code_bits(dst);
-    for (uint32_t f = 0; f < rec->nf; ++f) {
-      uint64_t end = 8 * orc_blob_size(rec, dst, n, f);
-      for (uint64_t q = n * B; q < end; ++q) dblobs[f][q >> 3] &= (uint8_t)~(1u << (q & 7));
-    }
-  }
+  clear_stream_tails(rec, dst, dblobs, n);
   return 0;
 }
 

@@ -189,3 +189,55 @@ def test_aosoa_padding_untouched():
     for f in range(7):
         base = 2 * 112 + f * 16
         assert np.all(blob[base + 8: base + 16] == 0xA5)
+
+
+# ---------------------------------------------------------------- Split and Null (Sec. 3)
+
+def test_split_blobs_equal_numpy_parts():
+    """Split(3, AoS, SoA-MB) over 7 x f32: blob 0 is the packed AoS of fields 0..2,
+    blobs 1..4 are the raw planes of fields 3..6 (numpy closed forms)."""
+    rng = np.random.default_rng(21)
+    n = 53
+    rec = ["f32"] * 7
+    planes = [rng.integers(0, 2 ** 32, n, dtype=np.uint64).astype(np.uint32) for _ in range(7)]
+    spec = {"kind": "split", "at": 3, "parts": [{"kind": "aos"}, {"kind": "soa_mb"}]}
+    assert oracle.blob_count(rec, spec) == 5
+    blobs = oracle.store_planes(rec, spec, [p.view(np.float32) for p in planes])
+    aos = np.stack(planes[:3], axis=1).astype("<u4").view(np.uint8).reshape(-1)
+    assert np.array_equal(blobs[0], aos)
+    for f in range(3, 7):
+        assert np.array_equal(blobs[f - 2], planes[f].astype("<u4").view(np.uint8))
+
+
+def test_split_with_null_part_and_nesting():
+    rng = np.random.default_rng(22)
+    n = 40
+    rec = ["f64", "f64", "i32", "i32", "u8"]
+    planes = [rng.integers(0, 2 ** 63, n, dtype=np.uint64).view(np.float64) for _ in range(2)] + \
+             [rng.integers(-2 ** 31, 2 ** 31, n, dtype=np.int64).astype(np.int32) for _ in range(2)] + \
+             [rng.integers(0, 256, n, dtype=np.uint64).astype(np.uint8)]
+    inner = {"kind": "split", "at": 2, "parts": [{"kind": "soa_sb"}, {"kind": "null"}]}
+    spec = {"kind": "split", "at": 2, "parts": [{"kind": "aos"}, inner]}
+    # blobs: AoS of the two f64, SoA-SB of the two i32; the u8 field is dropped
+    assert oracle.blob_sizes(rec, spec, n) == [16 * n, 8 * n]
+    blobs = oracle.store_planes(rec, spec, planes)
+    assert np.array_equal(blobs[0], np.stack([p.view(np.uint64) for p in planes[:2]], 1).view(np.uint8).reshape(-1))
+    assert np.array_equal(blobs[1], np.concatenate([planes[2].view(np.uint8), planes[3].view(np.uint8)]))
+    back = oracle.copy(rec, spec, blobs, {"kind": "soa_mb"}, n, fill=0x77)
+    for f in range(4):
+        assert np.array_equal(back[f], np.ascontiguousarray(planes[f]).view(np.uint8))
+    assert not back[4].any()  # a Null field reads as zero
+
+
+def test_null_source_and_destination():
+    rec = ["f32"] * 3
+    n = 77
+    assert oracle.blob_count(rec, {"kind": "null"}) == 0
+    for dst in ({"kind": "aos"}, {"kind": "aosoa", "lanes": 8}, {"kind": "soa_sb"}):
+        out = oracle.copy(rec, {"kind": "null"}, [], dst, n, fill=0xA5)
+        mapped = oracle.copy(rec, {"kind": "soa_mb"}, [np.full(4 * n, 0xFF, np.uint8)] * 3, dst, n, fill=0xA5)
+        for o, m in zip(out, mapped):
+            # every mapped byte becomes 0; bytes no field maps (AoSoA padding) keep the fill
+            assert np.array_equal(o, np.where(m == 0xFF, 0, 0xA5).astype(np.uint8))
+    src = oracle.store_planes(rec, {"kind": "aos"}, [np.arange(n, dtype=np.float32)] * 3)
+    assert oracle.copy(rec, {"kind": "aos"}, src, {"kind": "null"}, n) == []
