@@ -115,6 +115,21 @@ typedef enum llama_map_kind {
                                       its top M payload bits and the quiet bit
                                       set (M = 0 turns NaN into Inf).  Decoding
                                       is exact.                                 */
+  /* Meta-mappings (Sec. 3). */
+  LLAMA_MAP_NULL = 8,              /* no blobs: loads give zero, stores are
+                                      dropped.  On the GPU a copy from NULL
+                                      writes zero to every mapped byte of the
+                                      destination (AoSoA padding untouched) and
+                                      a copy to NULL does nothing.            */
+  LLAMA_MAP_SPLIT = 9,             /* the first `lanes` leaf fields (1 <= lanes
+                                      < n_fields) are placed by inner[0], the
+                                      rest by inner[1]: `inner` points to an
+                                      array of two mappings.  Blobs: inner[0]'s,
+                                      then inner[1]'s.  On the GPU a SPLIT copies
+                                      to or from another SPLIT with the same
+                                      split point, SOA_MB or NULL, one copy per
+                                      part (UNSUPPORTED otherwise; batches take
+                                      no SPLIT or NULL views).                 */
 } llama_map_kind;
 
 #define LLAMA_FLAG_AOS_PACKED 0x1u /* AOS: no alignment padding between fields */

@@ -31,7 +31,7 @@ LIB_PATH = os.path.join(HERE, "libllama_mi.so")
 SCALARS = {"f32": 0, "f64": 1, "i8": 2, "u8": 3, "i16": 4, "u16": 5, "i32": 6, "u32": 7,
            "i64": 8, "u64": 9, "f16": 10, "bf16": 11}
 KINDS = {"aos": 0, "soa_sb": 1, "soa_mb": 2, "aosoa": 3, "bytesplit": 4, "changetype": 5,
-         "bitpack_int": 6, "bitpack_float": 7}
+         "bitpack_int": 6, "bitpack_float": 7, "null": 8, "split": 9}
 INDEX_TYPES = {"i16": 0, "u16": 1, "i32": 2, "u32": 3, "i64": 4, "u64": 5}
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "UNSUPPORTED", -3: "INDEX_OVERFLOW",
           -4: "RECORD_MISMATCH", -5: "ALIGNMENT", -6: "HIP", -7: "NO_MEMORY"}
@@ -150,6 +150,11 @@ def _mapping(spec, keep):
         m.stored_types = arr
     if "inner" in spec:
         m.inner = C.pointer(_mapping(spec["inner"], keep))
+    if spec["kind"] == "split":  # {"kind": "split", "at": k, "parts": [first, second]}
+        m.lanes = spec["at"]
+        parts = (_Mapping * 2)(_mapping(spec["parts"][0], keep), _mapping(spec["parts"][1], keep))
+        keep.append(parts)
+        m.inner = C.cast(parts, C.POINTER(_Mapping))
     keep.append(m)
     return m
 

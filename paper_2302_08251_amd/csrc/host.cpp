@@ -73,13 +73,14 @@ static Rec byte_record(const Rec& r) { return Rec(packed_size(r), LLAMA_U8); }
 
 static const char* kind_name(int k) {
   static const char* names[] = {"AOS", "SOA_SB", "SOA_MB", "AOSOA", "BYTESPLIT", "CHANGETYPE",
-                                "BITPACK_INT_SOA", "BITPACK_FLOAT_SOA"};
-  return (k >= 0 && k < 8) ? names[k] : "?";
+                                "BITPACK_INT_SOA", "BITPACK_FLOAT_SOA", "NULL", "SPLIT"};
+  return (k >= 0 && k < 10) ? names[k] : "?";
 }
 
 llama_status copy_mapping(const Rec& rec, const llama_mapping* map, MapDesc& out, int depth) {
   if (!map) return fail(LLAMA_ERR_INVALID_ARG, "mapping descriptor is NULL");
-  if ((int)map->kind < 0 || (int)map->kind > 7)
+  if (depth > 8) return fail(LLAMA_ERR_INVALID_ARG, "mappings nested more than 8 deep");
+  if ((int)map->kind < 0 || (int)map->kind > 9)
     return fail(LLAMA_ERR_INVALID_ARG, "unknown mapping kind " + std::to_string((int)map->kind));
   out.kind = map->kind;
   out.lanes = map->lanes;
@@ -137,6 +138,19 @@ llama_status copy_mapping(const Rec& rec, const llama_mapping* map, MapDesc& out
           return fail(LLAMA_ERR_INVALID_ARG, "BITPACK_INT_SOA bits must be in [1, bit width of every field]");
       }
       return LLAMA_OK;
+    case LLAMA_MAP_NULL:
+      return LLAMA_OK;
+    case LLAMA_MAP_SPLIT: {
+      if (!map->inner) return fail(LLAMA_ERR_INVALID_ARG, "SPLIT needs inner: an array of two mappings");
+      if (map->lanes < 1 || map->lanes >= rec.size())
+        return fail(LLAMA_ERR_INVALID_ARG, "SPLIT needs 1 <= lanes < the number of fields");
+      const Rec r0(rec.begin(), rec.begin() + map->lanes), r1(rec.begin() + map->lanes, rec.end());
+      out.inner.reset(new MapDesc);
+      out.inner2.reset(new MapDesc);
+      llama_status st = copy_mapping(r0, &map->inner[0], *out.inner, depth + 1);
+      if (st != LLAMA_OK) return st;
+      return copy_mapping(r1, &map->inner[1], *out.inner2, depth + 1);
+    }
     case LLAMA_MAP_BITPACK_FLOAT_SOA:
       for (auto t : rec) {
         if (!scalar_is_float(t)) return fail(LLAMA_ERR_INVALID_ARG, "BITPACK_FLOAT_SOA needs float fields");
@@ -162,6 +176,11 @@ uint32_t blob_count(const Rec& rec, const MapDesc& m) {
       return (uint32_t)rec.size();
     case LLAMA_MAP_BYTESPLIT: return blob_count(byte_record(rec), *m.inner);
     case LLAMA_MAP_CHANGETYPE: return blob_count(m.stored, *m.inner);
+    case LLAMA_MAP_NULL: return 0;
+    case LLAMA_MAP_SPLIT: {
+      const Rec r0(rec.begin(), rec.begin() + m.lanes), r1(rec.begin() + m.lanes, rec.end());
+      return blob_count(r0, *m.inner) + blob_count(r1, *m.inner2);
+    }
   }
   return 0;
 }
@@ -176,6 +195,12 @@ uint64_t blob_size(const Rec& rec, const MapDesc& m, uint64_t n, uint32_t b) {
     case LLAMA_MAP_CHANGETYPE: return blob_size(m.stored, *m.inner, n, b);
     case LLAMA_MAP_BITPACK_INT_SOA:
     case LLAMA_MAP_BITPACK_FLOAT_SOA: return 4 * ((n * code_bits(m) + 31) / 32);
+    case LLAMA_MAP_NULL: return 0;
+    case LLAMA_MAP_SPLIT: {
+      const Rec r0(rec.begin(), rec.begin() + m.lanes), r1(rec.begin() + m.lanes, rec.end());
+      const uint32_t c0 = blob_count(r0, *m.inner);
+      return b < c0 ? blob_size(r0, *m.inner, n, b) : blob_size(r1, *m.inner2, n, b - c0);
+    }
   }
   return 0;
 }
@@ -188,6 +213,11 @@ uint64_t mapped_bytes(const Rec& rec, const MapDesc& m, uint64_t n) {
     case LLAMA_MAP_CHANGETYPE: return n * packed_size(m.stored);
     case LLAMA_MAP_BITPACK_INT_SOA:
     case LLAMA_MAP_BITPACK_FLOAT_SOA: return rec.size() * ((n * code_bits(m) + 7) / 8);
+    case LLAMA_MAP_NULL: return 0;
+    case LLAMA_MAP_SPLIT: {
+      const Rec r0(rec.begin(), rec.begin() + m.lanes), r1(rec.begin() + m.lanes, rec.end());
+      return mapped_bytes(r0, *m.inner, n) + mapped_bytes(r1, *m.inner2, n);
+    }
   }
   return 0;
 }
@@ -334,6 +364,8 @@ llama_status make_side(const llama_view* v, Side& s, llama_scalar& user_t, llama
       if (s.bits > 32) return fail(LLAMA_ERR_UNSUPPORTED, "the GPU path packs codes of at most 32 bits");
       if (nf > kMaxCols) return fail(LLAMA_ERR_UNSUPPORTED, "more than 64 blobs in one view");
       break;
+    default:  // NULL and SPLIT are resolved before a copy reaches the tile engine
+      return fail(LLAMA_ERR_UNSUPPORTED, std::string("no tile-engine side for a ") + kind_name(m.kind) + " view");
   }
   s.blob_size = v->blob_bytes.empty() ? 0 : v->blob_bytes[0];
   for (size_t b = 0; b < v->blobs.size() && b < kMaxCols; ++b) s.blob[b] = v->blobs[b];
@@ -572,6 +604,31 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
   return LLAMA_OK;
 }
 
+llama_status plan_zero(const llama_view* dst, Plan& plan) {
+  plan = Plan{};
+  Side& D = plan.args.dst;
+  llama_scalar du, ds;
+  llama_status st = make_side(dst, D, du, ds);
+  if (st != LLAMA_OK) return st;
+  plan.kind = PK_ZERO;
+  plan.unit = D.layout == LY_STREAM ? 4u : D.cs;
+  plan.args.src = D;  // record count only
+  const uint64_t gran = tile_granule(D, D);
+  const uint64_t per = D.layout == LY_STREAM ? 0 : gran * D.rec_bytes;
+  uint64_t k = per ? 16384 / per : 32;
+  if (k < 1) k = 1;
+  while (k > 1 && gran * k * (D.layout == LY_STREAM ? 0 : D.rec_bytes) > 65536) --k;
+  const uint64_t tile = gran * k;
+  plan.args.tile = (uint32_t)tile;
+  plan.ntiles = (dst->n + tile - 1) / tile;
+  if (plan.ntiles > 0xFFFFFFFFull) return fail(LLAMA_ERR_INDEX_OVERFLOW, "too many tiles");
+  plan.args.ntiles_lo = (uint32_t)plan.ntiles;
+  plan.grid = (uint32_t)plan.ntiles;
+  plan.lds = 0;
+  plan.alg_bytes = mapped_bytes(dst->rec, dst->map, dst->n);
+  return LLAMA_OK;
+}
+
 llama_status launch_plan(const Plan& plan, hipStream_t st) {
   if (plan.ntiles == 0) return LLAMA_OK;
   hipError_t e = hipSuccess;
@@ -579,6 +636,7 @@ llama_status launch_plan(const Plan& plan, hipStream_t st) {
     case PK_RAW: e = launch_raw(plan.args, plan.unit, raw_variant(plan.args, plan.unit), plan.grid, plan.lds, st); break;
     case PK_CONV: e = launch_conv(plan.args, plan.unit, plan.grid, plan.lds, st); break;
     case PK_PACK: e = launch_pack(plan.args, plan.grid, plan.lds, st); break;
+    case PK_ZERO: e = launch_zero(plan.args, plan.unit, plan.grid, st); break;
     case PK_UNPACK: e = launch_unpack(plan.args, plan.unit, plan.grid, plan.lds, st); break;
   }
   if (e != hipSuccess) return fail(LLAMA_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -645,7 +703,7 @@ llama_status llama_view_create(const llama_record* rec, const llama_mapping* map
   const uint32_t nb = blob_count(v->rec, v->map);
   if (n_blobs != nb)
     return fail(LLAMA_ERR_INVALID_ARG, "mapping uses " + std::to_string(nb) + " blobs, got " + std::to_string(n_blobs));
-  if (!blobs || !blob_bytes) return fail(LLAMA_ERR_INVALID_ARG, "blobs or blob_bytes is NULL");
+  if (nb > 0 && (!blobs || !blob_bytes)) return fail(LLAMA_ERR_INVALID_ARG, "blobs or blob_bytes is NULL");
   for (uint32_t b = 0; b < nb; ++b) {
     const uint64_t need = blob_size(v->rec, v->map, v->n, b);
     if (need > 0 && need - 1 > imax)
@@ -677,13 +735,92 @@ llama_status llama_view_records(const llama_view* view, uint64_t* n) {
   return LLAMA_OK;
 }
 
+static void clone_map(const MapDesc& a, MapDesc& b) {
+  b.kind = a.kind;
+  b.lanes = a.lanes;
+  b.bits = a.bits;
+  b.exp_bits = a.exp_bits;
+  b.man_bits = a.man_bits;
+  b.flags = a.flags;
+  b.stored = a.stored;
+  b.inner.reset();
+  b.inner2.reset();
+  if (a.inner) {
+    b.inner.reset(new MapDesc);
+    clone_map(*a.inner, *b.inner);
+  }
+  if (a.inner2) {
+    b.inner2.reset(new MapDesc);
+    clone_map(*a.inner2, *b.inner2);
+  }
+}
+
+// Part `part` (fields [0, k) or [k, F)) of a view that can be divided by
+// fields: a SPLIT at k, SOA_MB (one blob per field) or NULL.
+static bool part_view(const llama_view* v, uint32_t k, int part, llama_view& out) {
+  const Rec& rec = v->rec;
+  out.rec.assign(part ? rec.begin() + k : rec.begin(), part ? rec.end() : rec.begin() + k);
+  out.rank = 1;
+  out.extents[0] = v->n;
+  out.n = v->n;
+  out.index_type = v->index_type;
+  out.blobs.clear();
+  out.blob_bytes.clear();
+  size_t b0 = 0, b1 = 0;
+  if (v->map.kind == LLAMA_MAP_SPLIT) {
+    if (v->map.lanes != k) return false;
+    clone_map(part ? *v->map.inner2 : *v->map.inner, out.map);
+    const Rec r0(rec.begin(), rec.begin() + k);
+    const size_t c0 = blob_count(r0, *v->map.inner);
+    b0 = part ? c0 : 0;
+    b1 = part ? v->blobs.size() : c0;
+  } else if (v->map.kind == LLAMA_MAP_SOA_MB) {
+    out.map = MapDesc{};
+    out.map.kind = LLAMA_MAP_SOA_MB;
+    b0 = part ? k : 0;
+    b1 = part ? rec.size() : k;
+  } else if (v->map.kind == LLAMA_MAP_NULL) {
+    out.map = MapDesc{};
+    out.map.kind = LLAMA_MAP_NULL;
+  } else {
+    return false;
+  }
+  out.blobs.assign(v->blobs.begin() + b0, v->blobs.begin() + b1);
+  out.blob_bytes.assign(v->blob_bytes.begin() + b0, v->blob_bytes.begin() + b1);
+  return true;
+}
+
+// Copy with the meta-mappings resolved: a NULL destination drops the values,
+// a NULL source writes zeros, a SPLIT on either side runs one copy per part.
+static llama_status copy_views(const llama_view* src, llama_view* dst, const llama_launch_params* params,
+                               hipStream_t st) {
+  if (!src || !dst) return fail(LLAMA_ERR_INVALID_ARG, "view is NULL");
+  if (src->rec != dst->rec) return fail(LLAMA_ERR_RECORD_MISMATCH, "source and destination records differ");
+  if (src->n != dst->n) return fail(LLAMA_ERR_RECORD_MISMATCH, "source and destination record counts differ");
+  const bool ssplit = src->map.kind == LLAMA_MAP_SPLIT, dsplit = dst->map.kind == LLAMA_MAP_SPLIT;
+  if (dst->map.kind == LLAMA_MAP_NULL) return LLAMA_OK;
+  if (ssplit || dsplit) {
+    const uint32_t k = ssplit ? src->map.lanes : dst->map.lanes;
+    for (int part = 0; part < 2; ++part) {
+      llama_view ps, pd;
+      if (!part_view(src, k, part, ps) || !part_view(dst, k, part, pd))
+        return fail(LLAMA_ERR_UNSUPPORTED,
+                    "a SPLIT view copies to or from another SPLIT with the same split point, SOA_MB or NULL");
+      llama_status s = copy_views(&ps, &pd, params, st);
+      if (s != LLAMA_OK) return s;
+    }
+    return LLAMA_OK;
+  }
+  Plan plan;
+  llama_status s = src->map.kind == LLAMA_MAP_NULL ? plan_zero(dst, plan) : plan_copy(src, dst, params, plan);
+  if (s != LLAMA_OK) return s;
+  return launch_plan(plan, st);
+}
+
 llama_status llama_copy_ex(const llama_view* src, llama_view* dst, const llama_launch_params* params,
                            void* stream) {
   clear_error();
-  Plan plan;
-  llama_status st = plan_copy(src, dst, params, plan);
-  if (st != LLAMA_OK) return st;
-  return launch_plan(plan, (hipStream_t)stream);
+  return copy_views(src, dst, params, (hipStream_t)stream);
 }
 
 llama_status llama_copy(const llama_view* src, llama_view* dst, void* stream) {

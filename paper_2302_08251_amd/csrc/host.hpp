@@ -15,7 +15,8 @@ struct MapDesc {
   llama_map_kind kind = LLAMA_MAP_AOS;
   uint32_t lanes = 0, bits = 0, exp_bits = 0, man_bits = 0, flags = 0;
   std::vector<llama_scalar> stored;
-  std::unique_ptr<MapDesc> inner;
+  std::unique_ptr<MapDesc> inner;   // Bytesplit / ChangeType; Split: part 0
+  std::unique_ptr<MapDesc> inner2;  // Split: part 1
 };
 
 using Rec = std::vector<llama_scalar>;
@@ -51,7 +52,7 @@ struct llama_view {
 
 namespace lm {
 
-enum PlanKind : uint32_t { PK_RAW = 0, PK_CONV = 1, PK_PACK = 2, PK_UNPACK = 3 };
+enum PlanKind : uint32_t { PK_RAW = 0, PK_CONV = 1, PK_PACK = 2, PK_UNPACK = 3, PK_ZERO = 4 };
 
 struct Plan {
   PlanKind kind = PK_RAW;
@@ -78,6 +79,9 @@ uint32_t tile_lds_bytes(const Side& s, uint32_t tile);
 llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama_launch_params* p,
                        Plan& plan, uint32_t lds_cap = 0, bool fill = false);
 llama_status launch_plan(const Plan& plan, hipStream_t st);
+
+// Zero fill of every mapped byte of dst (a copy from a NULL view).
+llama_status plan_zero(const llama_view* dst, Plan& plan);
 
 Div make_div(uint32_t d);
 

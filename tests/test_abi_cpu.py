@@ -79,6 +79,12 @@ def test_descriptor_errors():
     assert err(c, F32x7, {"kind": "changetype", "stored": ["i32"] * 7, "inner": {"kind": "aos"}}) == "INVALID_ARG"
     assert err(c, ["f16"], {"kind": "changetype", "stored": ["bf16"], "inner": {"kind": "aos"}}) == "INVALID_ARG"
     assert err(c, F32x7, {"kind": "bytesplit", "inner": {"kind": "bytesplit", "inner": {"kind": "aos"}}}) == "INVALID_ARG"
+    # Split needs 1 <= at < fields and two parts; Null has no blobs
+    assert err(c, F32x7, {"kind": "split", "at": 0, "parts": [{"kind": "aos"}, {"kind": "aos"}]}) == "INVALID_ARG"
+    assert err(c, F32x7, {"kind": "split", "at": 7, "parts": [{"kind": "aos"}, {"kind": "aos"}]}) == "INVALID_ARG"
+    assert c(F32x7, {"kind": "split", "at": 3, "parts": [{"kind": "aos"}, {"kind": "soa_mb"}]}) == 5
+    assert c(F32x7, {"kind": "split", "at": 2, "parts": [{"kind": "null"}, {"kind": "soa_sb"}]}) == 1
+    assert c(F32x7, {"kind": "null"}) == 0
     # the rounding flag belongs to BitPackedFloatSoA only
     assert err(c, F32x7, {"kind": "aos", "round": "rne"}) == "INVALID_ARG"
     assert err(c, ["i32"], {"kind": "bitpack_int", "bits": 5, "round": "rne"}) == "INVALID_ARG"
