@@ -9,6 +9,9 @@ Mapping specs are plain dicts shared as *data* with the tests:
     {"kind": "aosoa", "lanes": 32}         {"kind": "bytesplit", "inner": spec}
     {"kind": "changetype", "stored": ["f32", ...], "inner": spec}
     {"kind": "bitpack_int", "bits": 12}    {"kind": "bitpack_float", "exp": 8, "man": 15}
+    {"kind": "null"}    {"kind": "split", "at": k, "parts": [spec, spec]}
+    {"kind": "field_access_count", "inner": spec}
+    {"kind": "heatmap", "granularity": G, "inner": spec}
 Records are lists of leaf type names: "f32", "f64", "i8" ... "u64", "f16", "bf16".
 """
 import ctypes as C
@@ -21,7 +24,8 @@ from . import build as _build
 _TYPES = {"f32": 0, "f64": 1, "i8": 2, "u8": 3, "i16": 4, "u16": 5, "i32": 6, "u32": 7,
           "i64": 8, "u64": 9, "f16": 10, "bf16": 11}
 _KINDS = {"aos": 0, "soa_sb": 1, "soa_mb": 2, "aosoa": 3, "bytesplit": 4, "changetype": 5,
-          "bitpack_int": 6, "bitpack_float": 7, "null": 8, "split": 9}
+          "bitpack_int": 6, "bitpack_float": 7, "null": 8, "split": 9, "field_access_count": 10,
+          "heatmap": 11}
 TYPE_SIZE = {"f32": 4, "f64": 8, "i8": 1, "u8": 1, "i16": 2, "u16": 2, "i32": 4, "u32": 4,
              "i64": 8, "u64": 8, "f16": 2, "bf16": 2}
 
@@ -110,7 +114,7 @@ def _rec(types, keep):
 def _map(spec, keep):
     m = _Map()
     m.kind = _KINDS[spec["kind"]]
-    m.lanes = spec.get("lanes", 0)
+    m.lanes = spec.get("lanes", spec.get("granularity", 0))
     m.bits = spec.get("bits", 0)
     m.exp_bits = spec.get("exp", 0)
     m.man_bits = spec.get("man", 0)

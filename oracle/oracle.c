@@ -289,6 +289,50 @@ static orc_rec split_part(const orc_rec* rec, const orc_map* m, int part) {
 }
 
 EXPORT uint32_t orc_blob_count(const orc_rec* rec, const orc_map* m);
+EXPORT uint64_t orc_blob_size(const orc_rec* rec, const orc_map* m, uint64_t n, uint32_t b);
+
+/* Instrumentation (Sec. 4).  Both mappings forward every location, load and
+ * store to the inner mapping and, as a side effect of each access, add one to
+ * counters held in extra blobs placed after the inner mapping's blobs:
+ *  - FieldAccessCount: one extra blob of 2F 64-bit counters; counter 2f counts
+ *    the loads of field f and counter 2f+1 its stores;
+ *  - Heatmap(G): one extra blob per inner blob b, holding one 64-bit counter
+ *    per G bytes of b.  An access to a field adds one to every counter whose
+ *    G bytes contain at least one byte of the field (loads and stores alike).
+ * The increments are atomic, so the parallel copy below counts exactly. */
+static void count_one(uint8_t* blob, uint64_t idx) {
+  __atomic_fetch_add((uint64_t*)(blob + 8 * idx), (uint64_t)1, __ATOMIC_RELAXED);
+}
+
+EXPORT int orc_locate(const orc_rec* rec, const orc_map* m, uint64_t n, uint64_t i, uint32_t f,
+                      uint32_t k, uint32_t* blob, uint64_t* off);
+
+static void count_access(const orc_rec* rec, const orc_map* m, uint64_t n, uint8_t* const* blobs,
+                         uint64_t i, uint32_t f, int is_store) {
+  const uint32_t c = orc_blob_count(rec, m->inner);
+  if (m->kind == ORC_FIELD_ACCESS_COUNT) {
+    count_one(blobs[c], 2ull * f + (is_store ? 1 : 0));
+    return;
+  }
+  /* Heatmap: the distinct (blob, counter) pairs over the field's bytes */
+  uint32_t cb[8];
+  uint64_t cg[8];
+  uint32_t nc = 0;
+  for (uint32_t k = 0; k < orc_type_size(rec->types[f]); ++k) {
+    uint32_t b;
+    uint64_t o;
+    orc_locate(rec, m->inner, n, i, f, k, &b, &o);
+    const uint64_t g = o / m->lanes;
+    int seen = 0;
+    for (uint32_t q = 0; q < nc; ++q) seen |= cb[q] == b && cg[q] == g;
+    if (!seen) {
+      cb[nc] = b;
+      cg[nc] = g;
+      ++nc;
+    }
+  }
+  for (uint32_t q = 0; q < nc; ++q) count_one(blobs[c + cb[q]], cg[q]);
+}
 
 EXPORT int orc_locate(const orc_rec* rec, const orc_map* m, uint64_t n, uint64_t i, uint32_t f,
                       uint32_t k, uint32_t* blob, uint64_t* off) {
@@ -328,6 +372,9 @@ EXPORT int orc_locate(const orc_rec* rec, const orc_map* m, uint64_t n, uint64_t
       *blob += orc_blob_count(&p0, &m->inner[0]);
       return rc;
     }
+    case ORC_FIELD_ACCESS_COUNT:
+    case ORC_HEATMAP:
+      return orc_locate(rec, m->inner, n, i, f, k, blob, off);
   }
   return -1;  /* Null and the computed mappings have no byte locations */
 }
@@ -343,6 +390,8 @@ EXPORT uint32_t orc_blob_count(const orc_rec* rec, const orc_map* m) {
       orc_rec p0 = split_part(rec, m, 0), p1 = split_part(rec, m, 1);
       return orc_blob_count(&p0, &m->inner[0]) + orc_blob_count(&p1, &m->inner[1]);
     }
+    case ORC_FIELD_ACCESS_COUNT: return orc_blob_count(rec, m->inner) + 1;
+    case ORC_HEATMAP: return 2 * orc_blob_count(rec, m->inner);
   }
   return 0;
 }
@@ -362,6 +411,15 @@ EXPORT uint64_t orc_blob_size(const orc_rec* rec, const orc_map* m, uint64_t n, 
       orc_rec p0 = split_part(rec, m, 0), p1 = split_part(rec, m, 1);
       const uint32_t c0 = orc_blob_count(&p0, &m->inner[0]);
       return b < c0 ? orc_blob_size(&p0, &m->inner[0], n, b) : orc_blob_size(&p1, &m->inner[1], n, b - c0);
+    }
+    case ORC_FIELD_ACCESS_COUNT: {
+      const uint32_t c = orc_blob_count(rec, m->inner);
+      return b < c ? orc_blob_size(rec, m->inner, n, b) : 16ull * rec->nf;
+    }
+    case ORC_HEATMAP: {
+      const uint32_t c = orc_blob_count(rec, m->inner);
+      if (b < c) return orc_blob_size(rec, m->inner, n, b);
+      return 8 * ((orc_blob_size(rec, m->inner, n, b - c) + m->lanes - 1) / m->lanes);
     }
   }
   return 0;
@@ -431,6 +489,10 @@ EXPORT uint64_t orc_load(const orc_rec* rec, const orc_map* m, uint64_t n, uint8
       orc_rec p1 = split_part(rec, m, 1);
       return orc_load(&p1, &m->inner[1], n, blobs + orc_blob_count(&p0, &m->inner[0]), i, f - m->lanes);
     }
+    case ORC_FIELD_ACCESS_COUNT:
+    case ORC_HEATMAP:
+      count_access(rec, m, n, blobs, i, f, 0);
+      return orc_load(rec, m->inner, n, blobs, i, f);
   }
   return 0;
 }
@@ -473,6 +535,11 @@ EXPORT void orc_store(const orc_rec* rec, const orc_map* m, uint64_t n, uint8_t*
       }
       return;
     }
+    case ORC_FIELD_ACCESS_COUNT:
+    case ORC_HEATMAP:
+      count_access(rec, m, n, blobs, i, f, 1);
+      orc_store(rec, m->inner, n, blobs, i, f, v);
+      return;
   }
 }
 
@@ -491,6 +558,10 @@ static void clear_stream_tails(const orc_rec* rec, const orc_map* m, uint8_t* co
     orc_rec p0 = split_part(rec, m, 0), p1 = split_part(rec, m, 1);
     clear_stream_tails(&p0, &m->inner[0], blobs, n);
     clear_stream_tails(&p1, &m->inner[1], blobs + orc_blob_count(&p0, &m->inner[0]), n);
+    return;
+  }
+  if (m->kind == ORC_FIELD_ACCESS_COUNT || m->kind == ORC_HEATMAP) {
+    clear_stream_tails(rec, m->inner, blobs, n);
     return;
   }
   if (!is_bitpacked(m)) return;
