@@ -258,6 +258,54 @@ def bench_cfg3(lm, torch, reps, n_vals, n_rec):
     return out
 
 
+# ------------------------------------------------------------------ instrumentation
+
+def bench_instr(lm, torch, reps, n):
+    """Sec. 4 instrumentation: the AoS -> SoA-SB copy of 7 x f32 records, plain and
+    with FieldAccessCount or Heatmap (G = 128 and G = 1) on both views; the
+    slowdown over the plain copy and the counter memory per view.  I64 index
+    everywhere: a G = 1 heatmap of these views holds 15 GB of counters."""
+    T = Timer(torch)
+    log("instr: AoS -> SoA-SB on %d records, plain and instrumented" % n)
+    rec = ["f32"] * 7
+    base = lm.View(rec, {"kind": "aos"}, [n], index_type="i64", fill=1)
+    out = {"records": n}
+    cases = [("plain", None), ("field_access_count", lambda m: {"kind": "field_access_count", "inner": m}),
+             ("heatmap_g128", lambda m: {"kind": "heatmap", "granularity": 128, "inner": m}),
+             ("heatmap_g1", lambda m: {"kind": "heatmap", "granularity": 1, "inner": m})]
+    t_plain = None
+    for name, wrap in cases:
+        sm, dm = {"kind": "aos"}, {"kind": "soa_sb"}
+        if wrap:
+            sm, dm = wrap(sm), wrap(dm)
+        if wrap:  # counters start at zero; the data blob holds the same records
+            s = lm.View(rec, sm, [n], index_type="i64", fill=0)
+            s.blobs[0].copy_(base.blobs[0][: s.sizes[0]])
+        else:
+            s = lm.View(rec, sm, [n], index_type="i64", blobs=[base.blobs[0]])
+        d = lm.View(rec, dm, [n], index_type="i64", fill=0)
+        t = float(np.median(T.time(lambda: lm.llama_copy(s, d), reps)))
+        row = {"ms": round(t, 4), "gbs": round(2 * 28 * n / t / 1e6, 1)}
+        counter_bytes = sum(s.sizes[1:]) if wrap else 0
+        if wrap:
+            row["counter_bytes_per_view"] = counter_bytes
+            row["memory_factor"] = round(counter_bytes / (28 * n), 3)
+        if t_plain is None:
+            t_plain = t
+        else:
+            row["slowdown"] = round(t / t_plain, 3)
+        if wrap and "heatmap" in name and t > t_plain:
+            # counters read and written once per copy, both views; time over the plain copy
+            row["counter_rmw_gbs"] = round(2 * 2 * counter_bytes / (t - t_plain) / 1e6, 1)
+        out[name] = row
+        s.close()
+        d.close()
+        del s, d
+        torch.cuda.empty_cache()
+    base.close()
+    return out
+
+
 # ------------------------------------------------------------------ cfg4: batched
 
 def bench_cfg4(lm, torch, reps, count):
@@ -397,7 +445,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--records", type=int, default=64 << 20)
-    ap.add_argument("--rows", default="cfg3,cfg4,cfg5", help="extra rows to measure (comma list or 'none')")
+    ap.add_argument("--rows", default="cfg3,cfg4,cfg5,instr", help="extra rows to measure (comma list or 'none')")
     ap.add_argument("--cpu-sample", type=int, default=4 << 20)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
@@ -416,7 +464,8 @@ def main():
     extra = {}
     row_fns = {"cfg3": lambda: bench_cfg3(lm, torch, max(3, args.steps), 256 << 20, 64 << 20),
                "cfg4": lambda: bench_cfg4(lm, torch, max(3, args.steps), 2000),
-               "cfg5": lambda: bench_cfg5(lm, torch, 65536, max(3, args.steps))}
+               "cfg5": lambda: bench_cfg5(lm, torch, 65536, max(3, args.steps)),
+               "instr": lambda: bench_instr(lm, torch, max(3, args.steps), 64 << 20)}
     for r in rows:
         try:
             extra[r] = row_fns[r]()

@@ -130,6 +130,28 @@ typedef enum llama_map_kind {
                                       split point, SOA_MB or NULL, one copy per
                                       part (UNSUPPORTED otherwise; batches take
                                       no SPLIT or NULL views).                 */
+  /* Instrumentation (Sec. 4): locations, loads and stores go to `inner`;
+   * every access also adds one to 64-bit counters held in extra blobs placed
+   * after the inner mapping's blobs.  The caller owns those blobs and zeroes
+   * them (or keeps counting across calls); a copy adds, it never clears.
+   * A copy adds its counts after its data kernels, on the same stream, one
+   * add per counter; copies that overlap in time on views sharing counter
+   * blobs race, as overlapping writes to any blob do. */
+  LLAMA_MAP_FIELD_ACCESS_COUNT = 10, /* one extra blob of 2*n_fields counters:
+                                        counter 2f counts the loads of field f,
+                                        counter 2f+1 its stores.  `inner`: any
+                                        mapping of kinds 0-7.  A copy loads
+                                        every field of every record of the
+                                        source once and stores it once into
+                                        the destination.                      */
+  LLAMA_MAP_HEATMAP = 11,            /* `lanes` = G, bytes per counter, a power
+                                        of two in [1, 2^20].  One extra blob per
+                                        inner blob b: ceil(size_b / G) counters;
+                                        counter g of b counts the accesses that
+                                        touch at least one of the bytes
+                                        [g*G, g*G+G) of blob b.  G = 1 costs 8
+                                        bytes of counters per byte.  `inner`:
+                                        AOS, SOA_SB, SOA_MB or AOSOA.          */
 } llama_map_kind;
 
 #define LLAMA_FLAG_AOS_PACKED 0x1u /* AOS: no alignment padding between fields */
@@ -143,13 +165,14 @@ typedef enum llama_map_kind {
 
 typedef struct llama_mapping {
   llama_map_kind kind;
-  uint32_t lanes;     /* AOSOA: L >= 1                                              */
+  uint32_t lanes;     /* AOSOA: L >= 1; SPLIT: split point; HEATMAP: G               */
   uint32_t bits;      /* BITPACK_INT: 1 <= B <= bit width of every field type        */
   uint32_t exp_bits;  /* BITPACK_FLOAT: 2 <= E <= exponent width of every field type  */
   uint32_t man_bits;  /* BITPACK_FLOAT: 0 <= M <= mantissa width of every field type  */
   uint32_t flags;     /* LLAMA_FLAG_*                                               */
   const llama_scalar* stored_types;  /* CHANGETYPE: n_fields storage types          */
-  const struct llama_mapping* inner; /* BYTESPLIT / CHANGETYPE: forwarded mapping   */
+  const struct llama_mapping* inner; /* BYTESPLIT / CHANGETYPE / instrumentation:
+                                        forwarded mapping; SPLIT: array of two    */
 } llama_mapping;
 
 typedef struct llama_view llama_view;   /* opaque */

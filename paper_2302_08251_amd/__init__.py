@@ -12,6 +12,9 @@ Records are lists of leaf type names ("f32", "f64", "i8" ... "u64", "f16",
     {"kind": "aosoa", "lanes": L}       {"kind": "bytesplit", "inner": mapping}
     {"kind": "changetype", "stored": [types...], "inner": mapping}
     {"kind": "bitpack_int", "bits": B}  {"kind": "bitpack_float", "exp": E, "man": M}
+    {"kind": "null"}    {"kind": "split", "at": k, "parts": [mapping, mapping]}
+    {"kind": "field_access_count", "inner": mapping}
+    {"kind": "heatmap", "granularity": G, "inner": mapping}
 """
 import ctypes as C
 import os
@@ -31,7 +34,8 @@ LIB_PATH = os.path.join(HERE, "libllama_mi.so")
 SCALARS = {"f32": 0, "f64": 1, "i8": 2, "u8": 3, "i16": 4, "u16": 5, "i32": 6, "u32": 7,
            "i64": 8, "u64": 9, "f16": 10, "bf16": 11}
 KINDS = {"aos": 0, "soa_sb": 1, "soa_mb": 2, "aosoa": 3, "bytesplit": 4, "changetype": 5,
-         "bitpack_int": 6, "bitpack_float": 7, "null": 8, "split": 9}
+         "bitpack_int": 6, "bitpack_float": 7, "null": 8, "split": 9, "field_access_count": 10,
+         "heatmap": 11}
 INDEX_TYPES = {"i16": 0, "u16": 1, "i32": 2, "u32": 3, "i64": 4, "u64": 5}
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "UNSUPPORTED", -3: "INDEX_OVERFLOW",
           -4: "RECORD_MISMATCH", -5: "ALIGNMENT", -6: "HIP", -7: "NO_MEMORY"}
@@ -139,7 +143,7 @@ def _record(types, keep):
 def _mapping(spec, keep):
     m = _Mapping()
     m.kind = KINDS[spec["kind"]]
-    m.lanes = spec.get("lanes", 0)
+    m.lanes = spec.get("lanes", spec.get("granularity", 0))
     m.bits = spec.get("bits", 0)
     m.exp_bits = spec.get("exp", 0)
     m.man_bits = spec.get("man", 0)

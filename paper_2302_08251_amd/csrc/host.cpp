@@ -73,14 +73,15 @@ static Rec byte_record(const Rec& r) { return Rec(packed_size(r), LLAMA_U8); }
 
 static const char* kind_name(int k) {
   static const char* names[] = {"AOS", "SOA_SB", "SOA_MB", "AOSOA", "BYTESPLIT", "CHANGETYPE",
-                                "BITPACK_INT_SOA", "BITPACK_FLOAT_SOA", "NULL", "SPLIT"};
-  return (k >= 0 && k < 10) ? names[k] : "?";
+                                "BITPACK_INT_SOA", "BITPACK_FLOAT_SOA", "NULL", "SPLIT",
+                                "FIELD_ACCESS_COUNT", "HEATMAP"};
+  return (k >= 0 && k < 12) ? names[k] : "?";
 }
 
 llama_status copy_mapping(const Rec& rec, const llama_mapping* map, MapDesc& out, int depth) {
   if (!map) return fail(LLAMA_ERR_INVALID_ARG, "mapping descriptor is NULL");
   if (depth > 8) return fail(LLAMA_ERR_INVALID_ARG, "mappings nested more than 8 deep");
-  if ((int)map->kind < 0 || (int)map->kind > 9)
+  if ((int)map->kind < 0 || (int)map->kind > 11)
     return fail(LLAMA_ERR_INVALID_ARG, "unknown mapping kind " + std::to_string((int)map->kind));
   out.kind = map->kind;
   out.lanes = map->lanes;
@@ -151,6 +152,21 @@ llama_status copy_mapping(const Rec& rec, const llama_mapping* map, MapDesc& out
       if (st != LLAMA_OK) return st;
       return copy_mapping(r1, &map->inner[1], *out.inner2, depth + 1);
     }
+    case LLAMA_MAP_FIELD_ACCESS_COUNT:
+    case LLAMA_MAP_HEATMAP: {
+      if (!map->inner) return fail(LLAMA_ERR_INVALID_ARG, std::string(kind_name(map->kind)) + " needs an inner mapping");
+      const int ik = (int)map->inner->kind;
+      if (map->kind == LLAMA_MAP_FIELD_ACCESS_COUNT && (ik < 0 || ik > (int)LLAMA_MAP_BITPACK_FLOAT_SOA))
+        return fail(LLAMA_ERR_INVALID_ARG, "FIELD_ACCESS_COUNT instruments mappings of kinds 0-7");
+      if (map->kind == LLAMA_MAP_HEATMAP) {
+        if (!is_physical(map->inner->kind))
+          return fail(LLAMA_ERR_INVALID_ARG, "HEATMAP instruments AOS, SOA_SB, SOA_MB or AOSOA");
+        if (map->lanes < 1 || map->lanes > (1u << 20) || (map->lanes & (map->lanes - 1)))
+          return fail(LLAMA_ERR_INVALID_ARG, "HEATMAP needs lanes = bytes per counter, a power of two in [1, 2^20]");
+      }
+      out.inner.reset(new MapDesc);
+      return copy_mapping(rec, map->inner, *out.inner, depth + 1);
+    }
     case LLAMA_MAP_BITPACK_FLOAT_SOA:
       for (auto t : rec) {
         if (!scalar_is_float(t)) return fail(LLAMA_ERR_INVALID_ARG, "BITPACK_FLOAT_SOA needs float fields");
@@ -181,6 +197,8 @@ uint32_t blob_count(const Rec& rec, const MapDesc& m) {
       const Rec r0(rec.begin(), rec.begin() + m.lanes), r1(rec.begin() + m.lanes, rec.end());
       return blob_count(r0, *m.inner) + blob_count(r1, *m.inner2);
     }
+    case LLAMA_MAP_FIELD_ACCESS_COUNT: return blob_count(rec, *m.inner) + 1;
+    case LLAMA_MAP_HEATMAP: return 2 * blob_count(rec, *m.inner);
   }
   return 0;
 }
@@ -201,6 +219,14 @@ uint64_t blob_size(const Rec& rec, const MapDesc& m, uint64_t n, uint32_t b) {
       const uint32_t c0 = blob_count(r0, *m.inner);
       return b < c0 ? blob_size(r0, *m.inner, n, b) : blob_size(r1, *m.inner2, n, b - c0);
     }
+    case LLAMA_MAP_FIELD_ACCESS_COUNT: {
+      const uint32_t c = blob_count(rec, *m.inner);
+      return b < c ? blob_size(rec, *m.inner, n, b) : 16ull * rec.size();
+    }
+    case LLAMA_MAP_HEATMAP: {
+      const uint32_t c = blob_count(rec, *m.inner);
+      return b < c ? blob_size(rec, *m.inner, n, b) : 8 * ((blob_size(rec, *m.inner, n, b - c) + m.lanes - 1) / m.lanes);
+    }
   }
   return 0;
 }
@@ -218,6 +244,8 @@ uint64_t mapped_bytes(const Rec& rec, const MapDesc& m, uint64_t n) {
       const Rec r0(rec.begin(), rec.begin() + m.lanes), r1(rec.begin() + m.lanes, rec.end());
       return mapped_bytes(r0, *m.inner, n) + mapped_bytes(r1, *m.inner2, n);
     }
+    case LLAMA_MAP_FIELD_ACCESS_COUNT:
+    case LLAMA_MAP_HEATMAP: return mapped_bytes(rec, *m.inner, n);
   }
   return 0;
 }
@@ -790,13 +818,113 @@ static bool part_view(const llama_view* v, uint32_t k, int part, llama_view& out
   return true;
 }
 
-// Copy with the meta-mappings resolved: a NULL destination drops the values,
-// a NULL source writes zeros, a SPLIT on either side runs one copy per part.
+static bool instrumented(const llama_view* v) {
+  return v->map.kind == LLAMA_MAP_FIELD_ACCESS_COUNT || v->map.kind == LLAMA_MAP_HEATMAP;
+}
+
+// The view an instrumentation mapping forwards to: its inner mapping over the
+// leading blobs.
+static void inner_view(const llama_view* v, llama_view& out) {
+  out.rec = v->rec;
+  clone_map(*v->map.inner, out.map);
+  out.rank = v->rank;
+  for (int d = 0; d < 8; ++d) out.extents[d] = v->extents[d];
+  out.n = v->n;
+  out.index_type = v->index_type;
+  const size_t c = blob_count(v->rec, *v->map.inner);
+  out.blobs.assign(v->blobs.begin(), v->blobs.begin() + c);
+  out.blob_bytes.assign(v->blob_bytes.begin(), v->blob_bytes.begin() + c);
+}
+
+static uint32_t log2u(uint64_t x) {
+  uint32_t l = 0;
+  while ((1ull << l) < x) ++l;
+  return l;
+}
+
+// Heatmap geometry of inner blob b of a physical mapping.
+static HeatGeo heat_geo(const Rec& rec, const MapDesc& m, uint64_t n, uint32_t b, uint32_t G) {
+  HeatGeo g;
+  g.n = n;
+  g.shift = log2u(G);
+  uint64_t p = 0, q = 0;
+  switch (m.kind) {
+    case LLAMA_MAP_AOS: {
+      const bool packed = m.flags & LLAMA_FLAG_AOS_PACKED;
+      g.period = packed ? packed_size(rec) : aligned_size(rec);
+      g.recs = 1;
+      for (size_t f = 0; f < rec.size(); ++f) {
+        const uint64_t s = scalar_size(rec[f]);
+        if (!packed) q = (q + s - 1) / s * s;
+        g.run_off[f] = q;
+        g.run_lsz[f] = log2u(s);
+        q += s;
+      }
+      g.nruns = (uint32_t)rec.size();
+      break;
+    }
+    case LLAMA_MAP_SOA_SB:
+    case LLAMA_MAP_AOSOA: {
+      const uint64_t R = m.kind == LLAMA_MAP_AOSOA ? m.lanes : n;
+      g.period = R * packed_size(rec);
+      g.recs = R;
+      for (size_t f = 0; f < rec.size(); ++f) {
+        g.run_off[f] = R * p;
+        g.run_lsz[f] = log2u(scalar_size(rec[f]));
+        p += scalar_size(rec[f]);
+      }
+      g.nruns = (uint32_t)rec.size();
+      break;
+    }
+    case LLAMA_MAP_SOA_MB:
+    default:
+      g.period = n * scalar_size(rec[b]);
+      g.recs = n;
+      g.run_off[0] = 0;
+      g.run_lsz[0] = log2u(scalar_size(rec[b]));
+      g.nruns = 1;
+      break;
+  }
+  return g;
+}
+
+// Adds the accesses of one copy to the counters of an instrumented view:
+// every field of every record loaded once (source) or stored once (dest).
+static void count_copy(const llama_view* v, bool store, hipStream_t st) {
+  if (v->n == 0) return;
+  const uint32_t c = blob_count(v->rec, *v->map.inner);
+  if (v->map.kind == LLAMA_MAP_FIELD_ACCESS_COUNT) {
+    launch_field_count(v->blobs[c], (uint32_t)v->rec.size(), store ? 1u : 0u, v->n, st);
+    return;
+  }
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  for (uint32_t b = 0; b < c; ++b) {
+    const uint64_t counters = v->blob_bytes[c + b] / 8;
+    if (counters == 0) continue;
+    launch_heatmap(v->blobs[c + b], counters, heat_geo(v->rec, *v->map.inner, v->n, b, v->map.lanes), cus, st);
+  }
+}
+
+// Copy with the meta-mappings resolved: an instrumented view forwards to its
+// inner view and counts afterwards, a NULL destination drops the values, a
+// NULL source writes zeros, a SPLIT on either side runs one copy per part.
 static llama_status copy_views(const llama_view* src, llama_view* dst, const llama_launch_params* params,
                                hipStream_t st) {
   if (!src || !dst) return fail(LLAMA_ERR_INVALID_ARG, "view is NULL");
   if (src->rec != dst->rec) return fail(LLAMA_ERR_RECORD_MISMATCH, "source and destination records differ");
   if (src->n != dst->n) return fail(LLAMA_ERR_RECORD_MISMATCH, "source and destination record counts differ");
+  if (instrumented(src) || instrumented(dst)) {
+    llama_view is, id;
+    if (instrumented(src)) inner_view(src, is);
+    if (instrumented(dst)) inner_view(dst, id);
+    llama_status s = copy_views(instrumented(src) ? &is : src, instrumented(dst) ? &id : dst, params, st);
+    if (s != LLAMA_OK) return s;
+    if (instrumented(src)) count_copy(src, false, st);
+    if (instrumented(dst)) count_copy(dst, true, st);
+    return LLAMA_OK;
+  }
   const bool ssplit = src->map.kind == LLAMA_MAP_SPLIT, dsplit = dst->map.kind == LLAMA_MAP_SPLIT;
   if (dst->map.kind == LLAMA_MAP_NULL) return LLAMA_OK;
   if (ssplit || dsplit) {
@@ -828,8 +956,8 @@ llama_status llama_copy(const llama_view* src, llama_view* dst, void* stream) {
 }
 
 static bool computed(const llama_view* v) {
-  return v->map.kind == LLAMA_MAP_CHANGETYPE || v->map.kind == LLAMA_MAP_BITPACK_INT_SOA ||
-         v->map.kind == LLAMA_MAP_BITPACK_FLOAT_SOA;
+  const llama_map_kind k = instrumented(v) ? v->map.inner->kind : v->map.kind;
+  return k == LLAMA_MAP_CHANGETYPE || k == LLAMA_MAP_BITPACK_INT_SOA || k == LLAMA_MAP_BITPACK_FLOAT_SOA;
 }
 
 llama_status llama_pack(const llama_view* src, llama_view* dst, void* stream) {

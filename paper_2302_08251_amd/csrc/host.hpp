@@ -83,6 +83,26 @@ llama_status launch_plan(const Plan& plan, hipStream_t st);
 // Zero fill of every mapped byte of dst (a copy from a NULL view).
 llama_status plan_zero(const llama_view* dst, Plan& plan);
 
+// Geometry of one blob of a physical layout for Heatmap counting: records
+// come in periods of `period` bytes holding `recs` records each (AoS: one
+// record; AoSoA: L; SoA: all n).  Inside a period, run f starts at byte
+// run_off[f] and holds the records' elements of 2^run_lsz[f] bytes back to
+// back.
+struct HeatGeo {
+  uint64_t n = 0;
+  uint64_t period = 0;
+  uint64_t recs = 0;
+  uint32_t nruns = 0;
+  uint32_t shift = 0;  // log2 of the bytes per counter
+  uint64_t run_off[kMaxFields] = {};
+  uint32_t run_lsz[kMaxFields] = {};
+};
+
+// counts[2f + which] += n for f < nf (FieldAccessCount after a copy).
+void launch_field_count(void* counts, uint32_t nf, uint32_t which, uint64_t n, hipStream_t st);
+// ctr[q] += accesses touching bytes [q G, q G + G) of the blob (Heatmap).
+void launch_heatmap(void* ctr, uint64_t ncounters, const HeatGeo& g, int num_cus, hipStream_t st);
+
 Div make_div(uint32_t d);
 
 }  // namespace lm

@@ -1,0 +1,97 @@
+// Access counters of the instrumentation mappings (Sec. 4): FieldAccessCount
+// and Heatmap.
+//
+// The paper counts with one atomic increment per access, made by the code
+// that accesses the view.  Here the copy kernels move whole tiles, so the
+// counters of a copy are added after it on the same stream, aggregated
+// instead of one per access.  A copy loads every field of every record of
+// the source once and stores it once into the destination.
+//  - FieldAccessCount: one atomic add of n per field counter.
+//  - Heatmap: each counter (G bytes of an inner blob) belongs to one thread.
+//    The thread counts the accesses that touch those bytes from the inner
+//    layout's geometry and adds them with a plain read-modify-write,
+//    skipping zeros.  Each counter is then touched once per copy, so the
+//    kernel is bound by HBM: 8 bytes read and 8 written per counter.
+#include "host.hpp"
+
+namespace lm {
+
+__global__ __launch_bounds__(64) void k_field_count(unsigned long long* counts, uint32_t nf, uint32_t which,
+                                                    unsigned long long n) {
+  const uint32_t f = threadIdx.x + blockIdx.x * blockDim.x;
+  if (f < nf) atomicAdd(counts + 2u * f + which, n);
+}
+
+// Accessed elements of one period k of the inner layout that meet the bytes
+// [lo, hi) of that period (0 <= lo < hi <= period).
+__device__ inline uint64_t period_hits(const HeatGeo& g, uint64_t k, uint64_t lo, uint64_t hi) {
+  const uint64_t left = g.n - k * g.recs;
+  const uint64_t rk = left < g.recs ? left : g.recs;  // records in this period
+  uint64_t c = 0;
+  for (uint32_t f = 0; f < g.nruns; ++f) {
+    const uint64_t o = g.run_off[f];
+    const uint64_t end = o + (rk << g.run_lsz[f]);
+    if (hi <= o || lo >= end) continue;
+    const uint64_t e0 = ((lo > o ? lo : o) - o) >> g.run_lsz[f];
+    const uint64_t e1 = ((hi < end ? hi : end) - 1 - o) >> g.run_lsz[f];
+    c += e1 - e0 + 1;
+  }
+  return c;
+}
+
+// floor(a / p) for a < 2^53 and p >= 1: the double quotient is within one of
+// the true one, and one step of integer correction makes it exact.
+__device__ inline uint64_t div_floor(uint64_t a, uint64_t p, double inv_p) {
+  uint64_t k = (uint64_t)((double)a * inv_p);
+  if (k * p > a) --k;
+  else if ((k + 1) * p <= a) ++k;
+  return k;
+}
+
+__device__ inline uint64_t granule_hits(const HeatGeo& g, uint64_t q, uint64_t used, double inv_p) {
+  const uint64_t a = q << g.shift;
+  uint64_t b = a + (1ull << g.shift);
+  if (b > used) b = used;
+  if (a >= b) return 0;
+  const uint64_t k0 = div_floor(a, g.period, inv_p), k1 = div_floor(b - 1, g.period, inv_p);
+  if (k0 == k1) return period_hits(g, k0, a - k0 * g.period, b - k0 * g.period);
+  // the periods strictly between k0 and k1 are full
+  return period_hits(g, k0, a - k0 * g.period, g.period) + period_hits(g, k1, 0, b - k1 * g.period) +
+         (k1 - k0 - 1) * g.recs * g.nruns;
+}
+
+// Two adjacent counters per thread, read and written as one 16-byte access.
+// Every counter belongs to one thread of the launch, so a plain
+// read-modify-write is exact; launches that overlap in time on the same
+// counter blob race, as overlapping writes to any blob do.
+__global__ __launch_bounds__(256) void k_heatmap(unsigned long long* ctr, uint64_t ncounters, const HeatGeo g) {
+  const uint64_t nper = (g.n + g.recs - 1) / g.recs;  // periods holding records
+  const uint64_t used = nper * g.period;              // bytes of those periods
+  const double inv_p = 1.0 / (double)g.period;
+  const uint64_t npairs = ncounters / 2;
+  ulonglong2* c2 = reinterpret_cast<ulonglong2*>(ctr);
+  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < npairs;
+       t += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t h0 = granule_hits(g, 2 * t, used, inv_p), h1 = granule_hits(g, 2 * t + 1, used, inv_p);
+    if (h0 | h1) {
+      ulonglong2 v = c2[t];
+      v.x += h0;
+      v.y += h1;
+      c2[t] = v;
+    }
+  }
+  if ((ncounters & 1) && blockIdx.x == 0 && threadIdx.x == 0) ctr[ncounters - 1] += granule_hits(g, ncounters - 1, used, inv_p);
+}
+
+void launch_field_count(void* counts, uint32_t nf, uint32_t which, uint64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_field_count, dim3(1), dim3(64), 0, st, (unsigned long long*)counts, nf, which,
+                     (unsigned long long)n);
+}
+
+void launch_heatmap(void* ctr, uint64_t ncounters, const HeatGeo& g, int num_cus, hipStream_t st) {
+  const uint64_t want = (ncounters / 2 + 255) / 256, cap = (uint64_t)num_cus * 32;
+  const uint32_t grid = (uint32_t)(want < 1 ? 1 : want < cap ? want : cap);
+  hipLaunchKernelGGL(k_heatmap, dim3(grid), dim3(256), 0, st, (unsigned long long*)ctr, ncounters, g);
+}
+
+}  // namespace lm

@@ -46,6 +46,12 @@ def test_blob_sizes_match_oracle(rec, n):
     if all(t.startswith("f") for t in rec):
         specs.append({"kind": "changetype", "stored": ["f32"] * len(rec), "inner": {"kind": "soa_mb"}})
         specs.append({"kind": "bitpack_float", "exp": 5, "man": 10})
+    specs.append({"kind": "field_access_count", "inner": {"kind": "aosoa", "lanes": 3}})
+    specs.append({"kind": "field_access_count", "inner": {"kind": "bytesplit", "inner": {"kind": "soa_mb"}}})
+    for g in (1, 8, 128, 1 << 20):
+        specs.append({"kind": "heatmap", "granularity": g, "inner": {"kind": "aos"}})
+        specs.append({"kind": "heatmap", "granularity": g, "inner": {"kind": "soa_mb"}})
+    specs.append({"kind": "heatmap", "granularity": 64, "inner": {"kind": "aosoa", "lanes": 3}})
     for s in specs:
         assert lm.blob_sizes(rec, s, [n]) == oracle.blob_sizes(rec, s, n), s
     ints = ["i32", "u16", "i64"]
@@ -89,6 +95,21 @@ def test_descriptor_errors():
     assert err(c, F32x7, {"kind": "aos", "round": "rne"}) == "INVALID_ARG"
     assert err(c, ["i32"], {"kind": "bitpack_int", "bits": 5, "round": "rne"}) == "INVALID_ARG"
     assert c(["f32"], {"kind": "bitpack_float", "exp": 5, "man": 10, "round": "rne"}) == 1
+    # instrumentation (Sec. 4): FieldAccessCount over kinds 0-7, Heatmap over
+    # physical layouts with a power-of-two granularity up to 2^20
+    fac = lambda inner: {"kind": "field_access_count", "inner": inner}
+    heat = lambda g, inner: {"kind": "heatmap", "granularity": g, "inner": inner}
+    assert c(F32x7, fac({"kind": "soa_mb"})) == 8
+    assert c(F32x7, fac({"kind": "bitpack_float", "exp": 5, "man": 10})) == 8
+    assert err(c, F32x7, fac({"kind": "null"})) == "INVALID_ARG"
+    assert err(c, F32x7, fac(fac({"kind": "aos"}))) == "INVALID_ARG"
+    assert err(c, F32x7, {"kind": "field_access_count"}) == "INVALID_ARG"
+    assert c(F32x7, heat(1, {"kind": "soa_mb"})) == 14
+    assert c(F32x7, heat(1 << 20, {"kind": "aos"})) == 2
+    for g in (0, 3, 96, 1 << 21):
+        assert err(c, F32x7, heat(g, {"kind": "aos"})) == "INVALID_ARG", g
+    assert err(c, F32x7, heat(1, {"kind": "bytesplit", "inner": {"kind": "aos"}})) == "INVALID_ARG"
+    assert err(c, F32x7, heat(1, {"kind": "bitpack_float", "exp": 5, "man": 10})) == "INVALID_ARG"
     assert err(c, [], {"kind": "aos"}) == "INVALID_ARG"
     assert err(c, ["f32"] * 65, {"kind": "aos"}) == "INVALID_ARG"
 

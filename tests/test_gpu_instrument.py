@@ -1,0 +1,137 @@
+"""GPU parity of the instrumentation mappings (Sec. 4 FieldAccessCount and
+Heatmap) against the oracle, bit for bit: the copied bytes and every 64-bit
+counter, after one copy and after a second copy back that adds loads."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import F32x7, assert_blobs_equal, bits_planes, download, say, upload
+
+import paper_2302_08251_amd as lm
+
+pytestmark = pytest.mark.gpu
+
+# the tile engine takes records whose leaves have one size
+I16x3 = ["i16", "u16", "i16"]
+W8x3 = ["f64", "i64", "u64"]
+PHYS = [{"kind": "aos"}, {"kind": "aos", "packed": True}, {"kind": "soa_sb"}, {"kind": "soa_mb"},
+        {"kind": "aosoa", "lanes": 32}, {"kind": "aosoa", "lanes": 3}]
+
+
+def fac(inner):
+    return {"kind": "field_access_count", "inner": inner}
+
+
+def heat(inner, g):
+    return {"kind": "heatmap", "granularity": g, "inner": inner}
+
+
+def host_blobs(rec, spec, n, planes=None, fill=0xA5):
+    """Blobs of `spec` with zeroed counters; the inner blobs hold `planes` (or `fill`)."""
+    sizes = oracle.blob_sizes(rec, spec, n)
+    inner = spec.get("inner", spec) if spec["kind"] in ("field_access_count", "heatmap") else spec
+    nin = oracle.blob_count(rec, inner)
+    if planes is not None:
+        data = oracle.store_planes(rec, inner, planes, fill=0x5A)
+    else:
+        data = oracle.alloc_blobs(rec, inner, n, fill)
+    return data + [np.zeros(s, np.uint8) for s in sizes[nin:]]
+
+
+def view(rec, spec, n, blobs):
+    return lm.View(rec, spec, [n], blobs=upload(blobs))
+
+
+def round_trip(rec, a, b, n, seed):
+    """Copies a -> b, then b -> a into fresh data blobs whose counters are a's;
+    checks both views' blobs against the oracle after each copy."""
+    planes = bits_planes(n, rec, seed)
+    sh, dh = host_blobs(rec, a, n, planes), host_blobs(rec, b, n)
+    sv, dv = view(rec, a, n, sh), view(rec, b, n, dh)
+    lm.llama_copy(sv, dv)
+    oracle.copy(rec, a, sh, b, n, dst_blobs=dh)
+    assert_blobs_equal(download(sv), sh, "src %s -> %s n=%d" % (a, b, n))
+    assert_blobs_equal(download(dv), dh, "dst %s -> %s n=%d" % (a, b, n))
+    lm.llama_copy(dv, sv)
+    oracle.copy(rec, b, dh, a, n, dst_blobs=sh)
+    assert_blobs_equal(download(sv), sh, "back src %s <- %s n=%d" % (a, b, n))
+    assert_blobs_equal(download(dv), dh, "back dst %s <- %s n=%d" % (a, b, n))
+
+
+@pytest.mark.parametrize("n", [1, 1000, 40961])
+@pytest.mark.parametrize("rec", [F32x7, W8x3], ids=["f32x7", "w8x3"])
+def test_field_access_count(rec, n):
+    for a, b in ((fac({"kind": "aos"}), fac({"kind": "soa_sb"})), ({"kind": "soa_mb"}, fac({"kind": "aosoa", "lanes": 32})),
+                 (fac({"kind": "bytesplit", "inner": {"kind": "soa_sb"}}), {"kind": "aos"})):
+        say("fac", a, b, n)
+        round_trip(rec, a, b, n, seed=n)
+
+
+@pytest.mark.parametrize("n", [1, 1000, 40961])
+def test_field_access_count_computed(n):
+    rec = ["f32"] * 3
+    for a, b in (({"kind": "aos"}, fac({"kind": "bitpack_float", "exp": 6, "man": 9})),
+                 (fac({"kind": "soa_sb"}), fac({"kind": "changetype", "stored": ["f16"] * 3, "inner": {"kind": "aos"}}))):
+        say("fac computed", a, b, n)
+        planes = bits_planes(n, rec, seed=n + 1)
+        sh, dh = host_blobs(rec, a, n, planes), host_blobs(rec, b, n)
+        sv, dv = view(rec, a, n, sh), view(rec, b, n, dh)
+        lm.llama_copy(sv, dv)
+        oracle.copy(rec, a, sh, b, n, dst_blobs=dh)
+        assert_blobs_equal(download(sv), sh)
+        assert_blobs_equal(download(dv), dh)
+
+
+@pytest.mark.parametrize("g", [1, 4, 64, 128, 4096])
+@pytest.mark.parametrize("rec", [F32x7, I16x3], ids=["f32x7", "i16x3"])
+def test_heatmap_every_layout(rec, g):
+    for n in (1, 777, 40961):
+        for i, inner in enumerate(PHYS):
+            other = PHYS[(i + 2) % len(PHYS)]
+            say("heatmap", g, inner, other, n)
+            round_trip(rec, heat(inner, g), heat(other, max(1, g // 2)), n, seed=n + i)
+
+
+def test_heatmap_and_fac_together_and_empty():
+    n = 5000
+    round_trip(W8x3, heat({"kind": "aosoa", "lanes": 8}, 16), fac({"kind": "aos"}), n, seed=3)
+    sv, dv = lm.View(F32x7, fac({"kind": "aos"}), [0]), lm.View(F32x7, heat({"kind": "soa_sb"}, 1), [0])
+    sv.blobs[-1].zero_()
+    lm.llama_copy(sv, dv)
+    assert download(sv)[-1].view(np.uint64).tolist() == [0] * 14
+
+
+def test_full_size_heatmap_cache_lines():
+    """16 Mi records of 7 f32 (the copy benchmark's size), 128-byte counters on
+    both sides, against the oracle."""
+    n = 1 << 24
+    a, b = heat({"kind": "aos"}, 128), heat({"kind": "soa_sb"}, 128)
+    say("full-size heatmap", n)
+    planes = bits_planes(n, F32x7, seed=11)
+    sh, dh = host_blobs(F32x7, a, n, planes), host_blobs(F32x7, b, n)
+    sv, dv = view(F32x7, a, n, sh), view(F32x7, b, n, dh)
+    lm.llama_copy(sv, dv)
+    oracle.copy(F32x7, a, sh, b, n, dst_blobs=dh)
+    got_s, got_d = download(sv), download(dv)
+    assert_blobs_equal(got_s[1:], sh[1:], "source counters")
+    assert_blobs_equal(got_d, dh, "destination")
+
+
+def test_rejected_uses():
+    n = 100
+    with pytest.raises(lm.LlamaError) as e:
+        lm.View(F32x7, heat({"kind": "bytesplit", "inner": {"kind": "aos"}}, 1), [n])
+    assert e.value.name == "INVALID_ARG"
+    with pytest.raises(lm.LlamaError) as e:
+        lm.View(F32x7, heat({"kind": "aos"}, 3), [n])
+    assert e.value.name == "INVALID_ARG"
+    with pytest.raises(lm.LlamaError) as e:
+        lm.View(F32x7, fac({"kind": "split", "at": 2, "parts": [{"kind": "aos"}, {"kind": "aos"}]}), [n])
+    assert e.value.name == "INVALID_ARG"
+    sv, dv = lm.View(F32x7, fac({"kind": "aos"}), [n], fill=0), lm.View(F32x7, {"kind": "soa_sb"}, [n])
+    with pytest.raises(lm.LlamaError) as e:
+        lm.Batch([sv], [dv])
+    assert e.value.name == "UNSUPPORTED"
+    with pytest.raises(lm.LlamaError) as e:
+        lm.nbody_step(sv, 1, 0.01, 0.01)
+    assert e.value.name == "UNSUPPORTED"
