@@ -23,17 +23,19 @@ __global__ __launch_bounds__(64) void k_field_count(unsigned long long* counts, 
 }
 
 // Accessed elements of one period k of the inner layout that meet the bytes
-// [lo, hi) of that period (0 <= lo < hi <= period).
-__device__ inline uint64_t period_hits(const HeatGeo& g, uint64_t k, uint64_t lo, uint64_t hi) {
+// [lo, hi) of that period (0 <= lo < hi <= period).  T = uint32_t when the
+// period fits 32 bits.
+template <typename T>
+__device__ inline uint64_t period_hits(const HeatGeo& g, uint64_t k, T lo, T hi) {
   const uint64_t left = g.n - k * g.recs;
-  const uint64_t rk = left < g.recs ? left : g.recs;  // records in this period
-  uint64_t c = 0;
+  const T rk = (T)(left < g.recs ? left : g.recs);  // records in this period
+  T c = 0;
   for (uint32_t f = 0; f < g.nruns; ++f) {
-    const uint64_t o = g.run_off[f];
-    const uint64_t end = o + (rk << g.run_lsz[f]);
+    const T o = (T)g.run_off[f];
+    const T end = o + (rk << g.run_lsz[f]);
     if (hi <= o || lo >= end) continue;
-    const uint64_t e0 = ((lo > o ? lo : o) - o) >> g.run_lsz[f];
-    const uint64_t e1 = ((hi < end ? hi : end) - 1 - o) >> g.run_lsz[f];
+    const T e0 = ((lo > o ? lo : o) - o) >> g.run_lsz[f];
+    const T e1 = ((hi < end ? hi : end) - 1 - o) >> g.run_lsz[f];
     c += e1 - e0 + 1;
   }
   return c;
@@ -54,33 +56,68 @@ __device__ inline uint64_t granule_hits(const HeatGeo& g, uint64_t q, uint64_t u
   if (b > used) b = used;
   if (a >= b) return 0;
   const uint64_t k0 = div_floor(a, g.period, inv_p), k1 = div_floor(b - 1, g.period, inv_p);
-  if (k0 == k1) return period_hits(g, k0, a - k0 * g.period, b - k0 * g.period);
+  if (k0 == k1) return period_hits<uint64_t>(g, k0, a - k0 * g.period, b - k0 * g.period);
   // the periods strictly between k0 and k1 are full
-  return period_hits(g, k0, a - k0 * g.period, g.period) + period_hits(g, k1, 0, b - k1 * g.period) +
+  return period_hits<uint64_t>(g, k0, a - k0 * g.period, g.period) +
+         period_hits<uint64_t>(g, k1, 0, b - k1 * g.period) +
          (k1 - k0 - 1) * g.recs * g.nruns;
 }
 
-// Two adjacent counters per thread, read and written as one 16-byte access.
-// Every counter belongs to one thread of the launch, so a plain
-// read-modify-write is exact; launches that overlap in time on the same
-// counter blob race, as overlapping writes to any blob do.
+// Four adjacent counters per thread, read and written as two 16-byte
+// accesses.  When a counter is no wider than a period, the chunk's period
+// and offset come from one division and then advance by G; a counter that
+// straddles a period boundary (or a chunk of counters wider than periods)
+// takes the general path.  Every counter belongs to one thread of the
+// launch, so a plain read-modify-write is exact; launches that overlap in
+// time on the same counter blob race, as overlapping writes to any blob do.
+constexpr uint32_t kHeatChunk = 4;
+
+template <typename T>
 __global__ __launch_bounds__(256) void k_heatmap(unsigned long long* ctr, uint64_t ncounters, const HeatGeo g) {
   const uint64_t nper = (g.n + g.recs - 1) / g.recs;  // periods holding records
   const uint64_t used = nper * g.period;              // bytes of those periods
   const double inv_p = 1.0 / (double)g.period;
-  const uint64_t npairs = ncounters / 2;
+  const uint64_t G = 1ull << g.shift;
+  const uint64_t nchunks = ncounters / kHeatChunk;
   ulonglong2* c2 = reinterpret_cast<ulonglong2*>(ctr);
-  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < npairs;
+  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < nchunks;
        t += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t h0 = granule_hits(g, 2 * t, used, inv_p), h1 = granule_hits(g, 2 * t + 1, used, inv_p);
-    if (h0 | h1) {
-      ulonglong2 v = c2[t];
-      v.x += h0;
-      v.y += h1;
-      c2[t] = v;
+    const uint64_t q0 = t * kHeatChunk, a = q0 << g.shift;
+    uint64_t h[kHeatChunk];
+    if (G > g.period || a >= used) {
+#pragma unroll
+      for (uint32_t j = 0; j < kHeatChunk; ++j) h[j] = granule_hits(g, q0 + j, used, inv_p);
+    } else {
+      uint64_t k = div_floor(a, g.period, inv_p), lo = a - k * g.period;
+#pragma unroll
+      for (uint32_t j = 0; j < kHeatChunk; ++j) {
+        if (k >= nper) h[j] = 0;
+        else if (lo + G > g.period) h[j] = granule_hits(g, q0 + j, used, inv_p);
+        else h[j] = period_hits<T>(g, k, (T)lo, (T)(lo + G));
+        lo += G;
+        if (lo >= g.period) {
+          lo -= g.period;
+          ++k;
+        }
+      }
+    }
+    if (h[0] | h[1]) {
+      ulonglong2 v = c2[2 * t];
+      v.x += h[0];
+      v.y += h[1];
+      c2[2 * t] = v;
+    }
+    if (h[2] | h[3]) {
+      ulonglong2 v = c2[2 * t + 1];
+      v.x += h[2];
+      v.y += h[3];
+      c2[2 * t + 1] = v;
     }
   }
-  if ((ncounters & 1) && blockIdx.x == 0 && threadIdx.x == 0) ctr[ncounters - 1] += granule_hits(g, ncounters - 1, used, inv_p);
+  if (blockIdx.x == 0 && threadIdx.x < ncounters % kHeatChunk) {
+    const uint64_t q = nchunks * kHeatChunk + threadIdx.x;
+    ctr[q] += granule_hits(g, q, used, inv_p);
+  }
 }
 
 void launch_field_count(void* counts, uint32_t nf, uint32_t which, uint64_t n, hipStream_t st) {
@@ -89,9 +126,13 @@ void launch_field_count(void* counts, uint32_t nf, uint32_t which, uint64_t n, h
 }
 
 void launch_heatmap(void* ctr, uint64_t ncounters, const HeatGeo& g, int num_cus, hipStream_t st) {
-  const uint64_t want = (ncounters / 2 + 255) / 256, cap = (uint64_t)num_cus * 32;
+  const uint64_t want = (ncounters / kHeatChunk + 255) / 256, cap = (uint64_t)num_cus * 32;
   const uint32_t grid = (uint32_t)(want < 1 ? 1 : want < cap ? want : cap);
-  hipLaunchKernelGGL(k_heatmap, dim3(grid), dim3(256), 0, st, (unsigned long long*)ctr, ncounters, g);
+  // a period of at most 2^32 - 1 bytes keeps the in-period arithmetic in 32 bits
+  if (g.period <= 0xFFFFFFFFull)
+    hipLaunchKernelGGL(k_heatmap<uint32_t>, dim3(grid), dim3(256), 0, st, (unsigned long long*)ctr, ncounters, g);
+  else
+    hipLaunchKernelGGL(k_heatmap<uint64_t>, dim3(grid), dim3(256), 0, st, (unsigned long long*)ctr, ncounters, g);
 }
 
 }  // namespace lm
