@@ -135,3 +135,22 @@ def test_rejected_uses():
     with pytest.raises(lm.LlamaError) as e:
         lm.nbody_step(sv, 1, 0.01, 0.01)
     assert e.value.name == "UNSUPPORTED"
+
+
+def test_heatmap_soa_blob_beyond_4_gib():
+    """One SoA-SB period of 160 Mi + 3 records x 28 bytes (4.7 GB) takes the 64-bit
+    arithmetic.  SoA-SB of 4-byte leaves is dense and 4-byte aligned, so a counter of
+    G bytes sees (its bytes inside the blob) / 4 accesses; this closed form is the
+    one the oracle is pinned on for SoA granules."""
+    n, g = (160 << 20) + 3, 4096
+    say("heatmap beyond 4 GiB", n)
+    sv = lm.View(F32x7, {"kind": "aos"}, [n], fill=0)
+    dv = lm.View(F32x7, heat({"kind": "soa_sb"}, g), [n], fill=0)
+    lm.llama_copy(sv, dv)
+    got = download(dv)[1].view(np.uint64)
+    size = 28 * n
+    q = np.arange(got.size, dtype=np.int64)
+    want = (np.minimum(q * g + g, size) - q * g) // 4
+    assert np.array_equal(got, want.astype(np.uint64))
+    sv.close()
+    dv.close()
