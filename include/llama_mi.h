@@ -180,7 +180,9 @@ typedef struct llama_batch llama_batch; /* opaque */
 
 /* Number of blobs a mapping uses for a record (AOS, SOA_SB, AOSOA: 1;
  * SOA_MB: n_fields; BYTESPLIT/CHANGETYPE: the inner mapping's count over the
- * byte / storage record; BITPACK_*: n_fields). */
+ * byte / storage record; BITPACK_*: n_fields; NULL: 0; SPLIT: the sum of its
+ * parts'; FIELD_ACCESS_COUNT: the inner count + 1; HEATMAP: twice the inner
+ * count). */
 llama_status llama_mapping_blob_count(const llama_record* rec, const llama_mapping* map,
                                       uint32_t* n_blobs);
 
@@ -208,7 +210,11 @@ llama_status llama_view_records(const llama_view* view, uint64_t* n);
  * dst(i).f = src(i).f.  Both views must have the same record and N.  Between
  * physical mappings this moves bits (NaN payloads and denormals survive);
  * through computed mappings the values are encoded on store and decoded on
- * load.  AoSoA padding lanes of dst are never written. */
+ * load.  AoSoA padding lanes of dst are never written.  Meta-mappings and
+ * instrumentation: see LLAMA_MAP_NULL, _SPLIT, _FIELD_ACCESS_COUNT and
+ * _HEATMAP (an instrumented source counts loads even into a NULL dst).
+ * Errors: RECORD_MISMATCH (records or N differ), UNSUPPORTED (a pair the GPU
+ * kernels do not cover; nothing is launched), INVALID_ARG. */
 llama_status llama_copy(const llama_view* src, llama_view* dst, void* stream);
 
 /* Pack: src physical, dst computed (CHANGETYPE or BITPACK_*).  Unpack: src

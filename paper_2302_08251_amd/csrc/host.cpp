@@ -888,30 +888,51 @@ static HeatGeo heat_geo(const Rec& rec, const MapDesc& m, uint64_t n, uint32_t b
   return g;
 }
 
-// Adds the accesses of one copy to the counters of an instrumented view:
-// every field of every record loaded once (source) or stored once (dest).
-static void count_copy(const llama_view* v, bool store, hipStream_t st) {
+// One launch of a copy.  A copy is planned whole before its first launch, so
+// a pair that the kernels do not cover launches nothing.
+struct CopyStep {
+  enum Kind { DATA, FIELD_COUNT, HEAT } kind = DATA;
+  Plan plan;                 // DATA
+  void* counters = nullptr;  // FIELD_COUNT, HEAT
+  uint32_t nf = 0, which = 0;
+  uint64_t n = 0;            // FIELD_COUNT: records
+  uint64_t ncounters = 0;    // HEAT
+  HeatGeo geo;               // HEAT
+};
+
+// The counter updates of one copy on an instrumented view: every field of
+// every record loaded once (source) or stored once (destination).
+static void count_steps(const llama_view* v, bool store, std::vector<CopyStep>& steps) {
   if (v->n == 0) return;
   const uint32_t c = blob_count(v->rec, *v->map.inner);
   if (v->map.kind == LLAMA_MAP_FIELD_ACCESS_COUNT) {
-    launch_field_count(v->blobs[c], (uint32_t)v->rec.size(), store ? 1u : 0u, v->n, st);
+    CopyStep s;
+    s.kind = CopyStep::FIELD_COUNT;
+    s.counters = v->blobs[c];
+    s.nf = (uint32_t)v->rec.size();
+    s.which = store ? 1u : 0u;
+    s.n = v->n;
+    steps.push_back(s);
     return;
   }
-  int dev = 0, cus = 256;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   for (uint32_t b = 0; b < c; ++b) {
     const uint64_t counters = v->blob_bytes[c + b] / 8;
     if (counters == 0) continue;
-    launch_heatmap(v->blobs[c + b], counters, heat_geo(v->rec, *v->map.inner, v->n, b, v->map.lanes), cus, st);
+    CopyStep s;
+    s.kind = CopyStep::HEAT;
+    s.counters = v->blobs[c + b];
+    s.ncounters = counters;
+    s.geo = heat_geo(v->rec, *v->map.inner, v->n, b, v->map.lanes);
+    steps.push_back(s);
   }
 }
 
-// Copy with the meta-mappings resolved: an instrumented view forwards to its
-// inner view and counts afterwards, a NULL destination drops the values, a
-// NULL source writes zeros, a SPLIT on either side runs one copy per part.
-static llama_status copy_views(const llama_view* src, llama_view* dst, const llama_launch_params* params,
-                               hipStream_t st) {
+// Plans a copy with the meta-mappings resolved: an instrumented view forwards
+// to its inner view and counts afterwards, a NULL destination drops the
+// values, a NULL source writes zeros, a SPLIT on either side runs one copy
+// per part.
+static llama_status plan_views(const llama_view* src, const llama_view* dst, const llama_launch_params* params,
+                               std::vector<CopyStep>& steps) {
   if (!src || !dst) return fail(LLAMA_ERR_INVALID_ARG, "view is NULL");
   if (src->rec != dst->rec) return fail(LLAMA_ERR_RECORD_MISMATCH, "source and destination records differ");
   if (src->n != dst->n) return fail(LLAMA_ERR_RECORD_MISMATCH, "source and destination record counts differ");
@@ -919,10 +940,10 @@ static llama_status copy_views(const llama_view* src, llama_view* dst, const lla
     llama_view is, id;
     if (instrumented(src)) inner_view(src, is);
     if (instrumented(dst)) inner_view(dst, id);
-    llama_status s = copy_views(instrumented(src) ? &is : src, instrumented(dst) ? &id : dst, params, st);
+    llama_status s = plan_views(instrumented(src) ? &is : src, instrumented(dst) ? &id : dst, params, steps);
     if (s != LLAMA_OK) return s;
-    if (instrumented(src)) count_copy(src, false, st);
-    if (instrumented(dst)) count_copy(dst, true, st);
+    if (instrumented(src)) count_steps(src, false, steps);
+    if (instrumented(dst)) count_steps(dst, true, steps);
     return LLAMA_OK;
   }
   const bool ssplit = src->map.kind == LLAMA_MAP_SPLIT, dsplit = dst->map.kind == LLAMA_MAP_SPLIT;
@@ -934,15 +955,44 @@ static llama_status copy_views(const llama_view* src, llama_view* dst, const lla
       if (!part_view(src, k, part, ps) || !part_view(dst, k, part, pd))
         return fail(LLAMA_ERR_UNSUPPORTED,
                     "a SPLIT view copies to or from another SPLIT with the same split point, SOA_MB or NULL");
-      llama_status s = copy_views(&ps, &pd, params, st);
+      llama_status s = plan_views(&ps, &pd, params, steps);
       if (s != LLAMA_OK) return s;
     }
     return LLAMA_OK;
   }
-  Plan plan;
-  llama_status s = src->map.kind == LLAMA_MAP_NULL ? plan_zero(dst, plan) : plan_copy(src, dst, params, plan);
+  CopyStep step;
+  llama_status s = src->map.kind == LLAMA_MAP_NULL ? plan_zero(dst, step.plan) : plan_copy(src, dst, params, step.plan);
   if (s != LLAMA_OK) return s;
-  return launch_plan(plan, st);
+  steps.push_back(step);
+  return LLAMA_OK;
+}
+
+static llama_status copy_views(const llama_view* src, llama_view* dst, const llama_launch_params* params,
+                               hipStream_t st) {
+  std::vector<CopyStep> steps;
+  llama_status s = plan_views(src, dst, params, steps);
+  if (s != LLAMA_OK) return s;
+  int cus = 0;
+  for (const CopyStep& step : steps) {
+    switch (step.kind) {
+      case CopyStep::DATA:
+        if ((s = launch_plan(step.plan, st)) != LLAMA_OK) return s;
+        break;
+      case CopyStep::FIELD_COUNT:
+        launch_field_count(step.counters, step.nf, step.which, step.n, st);
+        break;
+      case CopyStep::HEAT:
+        if (cus <= 0) {
+          int dev = 0;
+          (void)hipGetDevice(&dev);
+          if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        }
+        launch_heatmap(step.counters, step.ncounters, step.geo, cus, st);
+        break;
+    }
+  }
+  return LLAMA_OK;
 }
 
 llama_status llama_copy_ex(const llama_view* src, llama_view* dst, const llama_launch_params* params,

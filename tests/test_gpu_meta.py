@@ -69,3 +69,18 @@ def test_null_destination_and_unsupported_pairs():
     with pytest.raises(lm.LlamaError) as e:
         lm.llama_copy(gpu_view(F32x7, SPLIT_A, n, fill=0), gpu_view(F32x7, other, n))
     assert e.value.name == "UNSUPPORTED"
+
+
+def test_unsupported_split_part_launches_nothing():
+    """Part 0 (AoS -> SoA-SB) is supported, part 1 (bit-packed -> bit-packed) is not:
+    the copy is planned whole first, so the destination stays untouched."""
+    n = 1000
+    a = {"kind": "split", "at": 3, "parts": [{"kind": "aos"}, {"kind": "bitpack_float", "exp": 5, "man": 10}]}
+    b = {"kind": "split", "at": 3, "parts": [{"kind": "soa_sb"}, {"kind": "bitpack_float", "exp": 8, "man": 7}]}
+    sv = gpu_view(F32x7, a, n, fill=0x11)
+    dv = gpu_view(F32x7, b, n, fill=0xA5)
+    with pytest.raises(lm.LlamaError) as e:
+        lm.llama_copy(sv, dv)
+    assert e.value.name == "UNSUPPORTED"
+    for blob in download(dv):
+        assert np.all(blob == 0xA5)
