@@ -154,3 +154,38 @@ def test_heatmap_soa_blob_beyond_4_gib():
     assert np.array_equal(got, want.astype(np.uint64))
     sv.close()
     dv.close()
+
+
+@pytest.mark.parametrize("n", [1, 3001])
+def test_instrumented_parts_and_null(n):
+    """Instrumentation composes with the meta-mappings: counted parts inside Splits,
+    loads counted when the destination is Null, stores counted when the source is."""
+    a = {"kind": "split", "at": 3, "parts": [fac({"kind": "aos"}), heat({"kind": "soa_mb"}, 4)]}
+    b = {"kind": "split", "at": 3, "parts": [{"kind": "soa_sb"}, fac({"kind": "aosoa", "lanes": 32})]}
+    say("split parts", n)
+    planes = bits_planes(n, F32x7, seed=n)
+    sh = oracle.store_planes(F32x7, a, planes, fill=0)
+    # blobs: AoS data, 2 x 3 counters | 4 SoA-MB planes, 4 counter blobs
+    for i in (1, 6, 7, 8, 9):
+        sh[i][:] = 0
+    dh = oracle.alloc_blobs(F32x7, b, n, 0xA5)
+    dh[-1][:] = 0
+    sv, dv = view(F32x7, a, n, sh), view(F32x7, b, n, dh)
+    lm.llama_copy(sv, dv)
+    oracle.copy(F32x7, a, sh, b, n, dst_blobs=dh)
+    assert_blobs_equal(download(sv), sh, "split source")
+    assert_blobs_equal(download(dv), dh, "split destination")
+    say("null ends", n)
+    null = {"kind": "null"}
+    fs = fac({"kind": "soa_sb"})
+    s2 = host_blobs(F32x7, fs, n, planes)
+    v2 = view(F32x7, fs, n, s2)
+    lm.llama_copy(v2, lm.View(F32x7, null, [n]))
+    oracle.copy(F32x7, fs, s2, null, n, dst_blobs=[])
+    assert_blobs_equal(download(v2), s2, "loads into null")
+    hd = heat({"kind": "aosoa", "lanes": 3}, 8)
+    d3 = host_blobs(F32x7, hd, n)
+    v3 = view(F32x7, hd, n, d3)
+    lm.llama_copy(lm.View(F32x7, null, [n]), v3)
+    oracle.copy(F32x7, null, [], hd, n, dst_blobs=d3)
+    assert_blobs_equal(download(v3), d3, "stores from null")
