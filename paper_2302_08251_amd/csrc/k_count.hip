@@ -50,16 +50,17 @@ __device__ inline uint64_t div_floor(uint64_t a, uint64_t p, double inv_p) {
   return k;
 }
 
+template <typename T>
 __device__ inline uint64_t granule_hits(const HeatGeo& g, uint64_t q, uint64_t used, double inv_p) {
   const uint64_t a = q << g.shift;
   uint64_t b = a + (1ull << g.shift);
   if (b > used) b = used;
   if (a >= b) return 0;
   const uint64_t k0 = div_floor(a, g.period, inv_p), k1 = div_floor(b - 1, g.period, inv_p);
-  if (k0 == k1) return period_hits<uint64_t>(g, k0, a - k0 * g.period, b - k0 * g.period);
+  if (k0 == k1) return period_hits<T>(g, k0, (T)(a - k0 * g.period), (T)(b - k0 * g.period));
   // the periods strictly between k0 and k1 are full
-  return period_hits<uint64_t>(g, k0, a - k0 * g.period, g.period) +
-         period_hits<uint64_t>(g, k1, 0, b - k1 * g.period) +
+  return period_hits<T>(g, k0, (T)(a - k0 * g.period), (T)g.period) +
+         period_hits<T>(g, k1, (T)0, (T)(b - k1 * g.period)) +
          (k1 - k0 - 1) * g.recs * g.nruns;
 }
 
@@ -86,13 +87,13 @@ __global__ __launch_bounds__(256) void k_heatmap(unsigned long long* ctr, uint64
     uint64_t h[kHeatChunk];
     if (G > g.period || a >= used) {
 #pragma unroll
-      for (uint32_t j = 0; j < kHeatChunk; ++j) h[j] = granule_hits(g, q0 + j, used, inv_p);
+      for (uint32_t j = 0; j < kHeatChunk; ++j) h[j] = granule_hits<T>(g, q0 + j, used, inv_p);
     } else {
       uint64_t k = div_floor(a, g.period, inv_p), lo = a - k * g.period;
 #pragma unroll
       for (uint32_t j = 0; j < kHeatChunk; ++j) {
         if (k >= nper) h[j] = 0;
-        else if (lo + G > g.period) h[j] = granule_hits(g, q0 + j, used, inv_p);
+        else if (lo + G > g.period) h[j] = granule_hits<T>(g, q0 + j, used, inv_p);
         else h[j] = period_hits<T>(g, k, (T)lo, (T)(lo + G));
         lo += G;
         if (lo >= g.period) {
@@ -116,7 +117,7 @@ __global__ __launch_bounds__(256) void k_heatmap(unsigned long long* ctr, uint64
   }
   if (blockIdx.x == 0 && threadIdx.x < ncounters % kHeatChunk) {
     const uint64_t q = nchunks * kHeatChunk + threadIdx.x;
-    ctr[q] += granule_hits(g, q, used, inv_p);
+    ctr[q] += granule_hits<T>(g, q, used, inv_p);
   }
 }
 
