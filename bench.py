@@ -297,6 +297,7 @@ def bench_instr(lm, torch, reps, n):
         if wrap and "heatmap" in name and t > t_plain:
             # counters read and written once per copy, both views; time over the plain copy
             row["counter_rmw_gbs"] = round(2 * 2 * counter_bytes / (t - t_plain) / 1e6, 1)
+            row["counter_frac_of_hbm_peak"] = round(row["counter_rmw_gbs"] / HBM_PEAK_GBS, 3)
         out[name] = row
         s.close()
         d.close()
