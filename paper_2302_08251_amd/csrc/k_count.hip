@@ -64,14 +64,17 @@ __device__ inline uint64_t granule_hits(const HeatGeo& g, uint64_t q, uint64_t u
          (k1 - k0 - 1) * g.recs * g.nruns;
 }
 
-// Four adjacent counters per thread, read and written as two 16-byte
-// accesses.  When a counter is no wider than a period, the chunk's period
-// and offset come from one division and then advance by G; a counter that
-// straddles a period boundary (or a chunk of counters wider than periods)
-// takes the general path.  Every counter belongs to one thread of the
-// launch, so a plain read-modify-write is exact; launches that overlap in
-// time on the same counter blob race, as overlapping writes to any blob do.
-constexpr uint32_t kHeatChunk = 4;
+// Counter pairs (16 bytes) per thread, read and written as one 16-byte
+// access, with consecutive lanes on consecutive pairs so that every wave
+// store writes 1 KiB of whole lines; a block covers kHeatRounds * 256 pairs
+// per grid-stride step.  When a counter is no wider than a period, the
+// pair's period and offset come from one division and the second counter
+// advances by G; a counter that straddles a period boundary (or is wider
+// than a period) takes the general path.  Every counter belongs to one
+// thread of the launch, so a plain read-modify-write is exact; launches
+// that overlap in time on the same counter blob race, as overlapping writes
+// to any blob do.
+constexpr uint32_t kHeatRounds = 2;
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_heatmap(unsigned long long* ctr, uint64_t ncounters, const HeatGeo g) {
@@ -79,46 +82,41 @@ __global__ __launch_bounds__(256) void k_heatmap(unsigned long long* ctr, uint64
   const uint64_t used = nper * g.period;              // bytes of those periods
   const double inv_p = 1.0 / (double)g.period;
   const uint64_t G = 1ull << g.shift;
-  const uint64_t nchunks = ncounters / kHeatChunk;
+  const uint64_t npairs = ncounters / 2;
+  const uint64_t step = (uint64_t)gridDim.x * blockDim.x * kHeatRounds;
   ulonglong2* c2 = reinterpret_cast<ulonglong2*>(ctr);
-  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < nchunks;
-       t += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t q0 = t * kHeatChunk, a = q0 << g.shift;
-    uint64_t h[kHeatChunk];
-    if (G > g.period || a >= used) {
+  for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x * kHeatRounds; base < npairs; base += step) {
 #pragma unroll
-      for (uint32_t j = 0; j < kHeatChunk; ++j) h[j] = granule_hits<T>(g, q0 + j, used, inv_p);
-    } else {
-      uint64_t k = div_floor(a, g.period, inv_p), lo = a - k * g.period;
-#pragma unroll
-      for (uint32_t j = 0; j < kHeatChunk; ++j) {
-        if (k >= nper) h[j] = 0;
-        else if (lo + G > g.period) h[j] = granule_hits<T>(g, q0 + j, used, inv_p);
-        else h[j] = period_hits<T>(g, k, (T)lo, (T)(lo + G));
+    for (uint32_t r = 0; r < kHeatRounds; ++r) {
+      const uint64_t p = base + r * blockDim.x + threadIdx.x;
+      if (p >= npairs) break;
+      const uint64_t q0 = 2 * p, a = q0 << g.shift;
+      uint64_t h0, h1;
+      if (G > g.period || a >= used) {
+        h0 = granule_hits<T>(g, q0, used, inv_p);
+        h1 = granule_hits<T>(g, q0 + 1, used, inv_p);
+      } else {
+        uint64_t k = div_floor(a, g.period, inv_p), lo = a - k * g.period;
+        h0 = lo + G > g.period ? granule_hits<T>(g, q0, used, inv_p) : period_hits<T>(g, k, (T)lo, (T)(lo + G));
         lo += G;
         if (lo >= g.period) {
           lo -= g.period;
           ++k;
         }
+        if (k >= nper) h1 = 0;
+        else if (lo + G > g.period) h1 = granule_hits<T>(g, q0 + 1, used, inv_p);
+        else h1 = period_hits<T>(g, k, (T)lo, (T)(lo + G));
+      }
+      if (h0 | h1) {
+        ulonglong2 v = c2[p];
+        v.x += h0;
+        v.y += h1;
+        c2[p] = v;
       }
     }
-    if (h[0] | h[1]) {
-      ulonglong2 v = c2[2 * t];
-      v.x += h[0];
-      v.y += h[1];
-      c2[2 * t] = v;
-    }
-    if (h[2] | h[3]) {
-      ulonglong2 v = c2[2 * t + 1];
-      v.x += h[2];
-      v.y += h[3];
-      c2[2 * t + 1] = v;
-    }
   }
-  if (blockIdx.x == 0 && threadIdx.x < ncounters % kHeatChunk) {
-    const uint64_t q = nchunks * kHeatChunk + threadIdx.x;
-    ctr[q] += granule_hits<T>(g, q, used, inv_p);
-  }
+  if ((ncounters & 1) && blockIdx.x == 0 && threadIdx.x == 0)
+    ctr[ncounters - 1] += granule_hits<T>(g, ncounters - 1, used, inv_p);
 }
 
 void launch_field_count(void* counts, uint32_t nf, uint32_t which, uint64_t n, hipStream_t st) {
@@ -127,7 +125,7 @@ void launch_field_count(void* counts, uint32_t nf, uint32_t which, uint64_t n, h
 }
 
 void launch_heatmap(void* ctr, uint64_t ncounters, const HeatGeo& g, int num_cus, hipStream_t st) {
-  const uint64_t want = (ncounters / kHeatChunk + 255) / 256, cap = (uint64_t)num_cus * 32;
+  const uint64_t want = (ncounters / 2 + 256 * kHeatRounds - 1) / (256 * kHeatRounds), cap = (uint64_t)num_cus * 32;
   const uint32_t grid = (uint32_t)(want < 1 ? 1 : want < cap ? want : cap);
   // a period of at most 2^32 - 1 bytes keeps the in-period arithmetic in 32 bits
   if (g.period <= 0xFFFFFFFFull)
