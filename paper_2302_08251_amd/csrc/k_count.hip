@@ -50,19 +50,24 @@ __device__ inline uint64_t div_floor(uint64_t a, uint64_t p, double inv_p) {
   return k;
 }
 
-template <typename T>
-__device__ inline uint64_t granule_hits(const HeatGeo& g, uint64_t q, uint64_t used, double inv_p) {
+template <typename Hits>
+__device__ inline uint64_t granule_hits(const HeatGeo& g, uint64_t q, uint64_t used, double inv_p, Hits hits) {
   const uint64_t a = q << g.shift;
   uint64_t b = a + (1ull << g.shift);
   if (b > used) b = used;
   if (a >= b) return 0;
   const uint64_t k0 = div_floor(a, g.period, inv_p), k1 = div_floor(b - 1, g.period, inv_p);
-  if (k0 == k1) return period_hits<T>(g, k0, (T)(a - k0 * g.period), (T)(b - k0 * g.period));
+  if (k0 == k1) return hits(k0, a - k0 * g.period, b - k0 * g.period);
   // the periods strictly between k0 and k1 are full
-  return period_hits<T>(g, k0, (T)(a - k0 * g.period), (T)g.period) +
-         period_hits<T>(g, k1, (T)0, (T)(b - k1 * g.period)) +
+  return hits(k0, a - k0 * g.period, g.period) + hits(k1, 0, b - k1 * g.period) +
          (k1 - k0 - 1) * g.recs * g.nruns;
 }
+
+// Periods of at most kHeatTable bytes get two per-byte tables in LDS, built
+// by each block: A[x] = elements of a full period that start before byte x,
+// B[x] = elements that end at or before x.  The elements meeting [lo, hi)
+// are then A[hi] - B[lo]; the last, partial period keeps the loop.
+constexpr uint32_t kHeatTable = 2048;
 
 // Counter pairs (16 bytes) per thread, read and written as one 16-byte
 // access, with consecutive lanes on consecutive pairs so that every wave
@@ -85,6 +90,32 @@ __global__ __launch_bounds__(256) void k_heatmap(unsigned long long* ctr, uint64
   const uint64_t npairs = ncounters / 2;
   const uint64_t step = (uint64_t)gridDim.x * blockDim.x * kHeatRounds;
   ulonglong2* c2 = reinterpret_cast<ulonglong2*>(ctr);
+  __shared__ uint32_t tA[kHeatTable + 1], tB[kHeatTable + 1];
+  // a block builds its tables at (period + 1) * runs steps: bounded so that
+  // wide records with long periods keep the loop instead
+  const bool table = g.period <= kHeatTable && (g.period + 1) * g.nruns <= 16384;
+  const uint64_t nfull = g.n / g.recs;  // periods holding g.recs records
+  if (table) {
+    const uint32_t P = (uint32_t)g.period, R = (uint32_t)g.recs;
+    for (uint32_t x = threadIdx.x; x <= P; x += blockDim.x) {
+      uint32_t ca = 0, cb = 0;
+      for (uint32_t f = 0; f < g.nruns; ++f) {
+        const uint32_t o = (uint32_t)g.run_off[f], l = g.run_lsz[f];
+        if (x <= o) continue;
+        const uint32_t d = x - o;
+        const uint32_t sa = (d + (1u << l) - 1u) >> l, sb = d >> l;
+        ca += sa < R ? sa : R;
+        cb += sb < R ? sb : R;
+      }
+      tA[x] = ca;
+      tB[x] = cb;
+    }
+    __syncthreads();
+  }
+  auto hits = [&](uint64_t k, uint64_t lo, uint64_t hi) -> uint64_t {
+    if (table && k < nfull) return (uint64_t)(tA[hi] - tB[lo]);
+    return period_hits<T>(g, k, (T)lo, (T)hi);
+  };
   for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x * kHeatRounds; base < npairs; base += step) {
 #pragma unroll
     for (uint32_t r = 0; r < kHeatRounds; ++r) {
@@ -93,19 +124,19 @@ __global__ __launch_bounds__(256) void k_heatmap(unsigned long long* ctr, uint64
       const uint64_t q0 = 2 * p, a = q0 << g.shift;
       uint64_t h0, h1;
       if (G > g.period || a >= used) {
-        h0 = granule_hits<T>(g, q0, used, inv_p);
-        h1 = granule_hits<T>(g, q0 + 1, used, inv_p);
+        h0 = granule_hits(g, q0, used, inv_p, hits);
+        h1 = granule_hits(g, q0 + 1, used, inv_p, hits);
       } else {
         uint64_t k = div_floor(a, g.period, inv_p), lo = a - k * g.period;
-        h0 = lo + G > g.period ? granule_hits<T>(g, q0, used, inv_p) : period_hits<T>(g, k, (T)lo, (T)(lo + G));
+        h0 = lo + G > g.period ? granule_hits(g, q0, used, inv_p, hits) : hits(k, lo, lo + G);
         lo += G;
         if (lo >= g.period) {
           lo -= g.period;
           ++k;
         }
         if (k >= nper) h1 = 0;
-        else if (lo + G > g.period) h1 = granule_hits<T>(g, q0 + 1, used, inv_p);
-        else h1 = period_hits<T>(g, k, (T)lo, (T)(lo + G));
+        else if (lo + G > g.period) h1 = granule_hits(g, q0 + 1, used, inv_p, hits);
+        else h1 = hits(k, lo, lo + G);
       }
       if (h0 | h1) {
         ulonglong2 v = c2[p];
@@ -116,7 +147,7 @@ __global__ __launch_bounds__(256) void k_heatmap(unsigned long long* ctr, uint64
     }
   }
   if ((ncounters & 1) && blockIdx.x == 0 && threadIdx.x == 0)
-    ctr[ncounters - 1] += granule_hits<T>(g, ncounters - 1, used, inv_p);
+    ctr[ncounters - 1] += granule_hits(g, ncounters - 1, used, inv_p, hits);
 }
 
 void launch_field_count(void* counts, uint32_t nf, uint32_t which, uint64_t n, hipStream_t st) {
