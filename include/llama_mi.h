@@ -178,7 +178,13 @@ typedef struct llama_mapping {
 typedef struct llama_view llama_view;   /* opaque */
 typedef struct llama_batch llama_batch; /* opaque */
 
-/* Number of blobs a mapping uses for a record (AOS, SOA_SB, AOSOA: 1;
+/* Sec. 2 separates a view's blobs from the allocator that provides them: a
+ * mapping only states how many blobs it needs and how large each one is,
+ * and the caller allocates them.  The next two calls answer those questions.
+ * Errors: INVALID_ARG (malformed record or mapping, NULL output, blob index
+ * out of range), INDEX_OVERFLOW (extents overflow 64 bits).
+ *
+ * Number of blobs a mapping uses for a record (AOS, SOA_SB, AOSOA: 1;
  * SOA_MB: n_fields; BYTESPLIT/CHANGETYPE: the inner mapping's count over the
  * byte / storage record; BITPACK_*: n_fields; NULL: 0; SPLIT: the sum of its
  * parts'; FIELD_ACCESS_COUNT: the inner count + 1; HEATMAP: twice the inner
@@ -186,7 +192,9 @@ typedef struct llama_batch llama_batch; /* opaque */
 llama_status llama_mapping_blob_count(const llama_record* rec, const llama_mapping* map,
                                       uint32_t* n_blobs);
 
-/* Byte size of blob `blob` for the given extents (rank 1..8). */
+/* Byte size of blob `blob` for the given extents (rank 1..8), row-major
+ * unless the mapping sets LLAMA_FLAG_COL_MAJOR (the size does not depend on
+ * the order). */
 llama_status llama_mapping_blob_size(const llama_record* rec, const llama_mapping* map,
                                      uint32_t rank, const uint64_t* extents, uint32_t blob,
                                      uint64_t* bytes);
@@ -201,6 +209,10 @@ llama_status llama_view_create(const llama_record* rec, const llama_mapping* map
                                llama_index_type index_type, void* const* blobs,
                                const uint64_t* blob_bytes, uint32_t n_blobs,
                                llama_view** out);
+/* Destroys a view handle (Sec. 1: a view binds a mapping to blobs it does
+ * not own).  The blobs are untouched and stay the caller's.  NULL is a no-op.
+ * Work already enqueued on a stream keeps its own copy of the descriptors,
+ * so a view may be destroyed before that work completes. */
 llama_status llama_view_destroy(llama_view* view);
 
 /* Number of records of a view. */
@@ -217,9 +229,13 @@ llama_status llama_view_records(const llama_view* view, uint64_t* n);
  * kernels do not cover; nothing is launched), INVALID_ARG. */
 llama_status llama_copy(const llama_view* src, llama_view* dst, void* stream);
 
-/* Pack: src physical, dst computed (CHANGETYPE or BITPACK_*).  Unpack: src
- * computed, dst physical.  Otherwise LLAMA_ERR_UNSUPPORTED.  Same semantics
- * as llama_copy. */
+/* Sec. 3 computed mappings convert values when they are stored to memory
+ * (pack) and when they are loaded from it (unpack).  Pack: src physical,
+ * dst computed (CHANGETYPE, BITPACK_INT_SOA or BITPACK_FLOAT_SOA): every
+ * value of src is encoded through dst's mapping.  Unpack: src computed, dst
+ * physical: every code of src is decoded into dst.  Otherwise UNSUPPORTED,
+ * and nothing is enqueued.  Layouts, ownership, streams and the other errors
+ * are as for llama_copy. */
 llama_status llama_pack(const llama_view* src, llama_view* dst, void* stream);
 llama_status llama_unpack(const llama_view* src, llama_view* dst, void* stream);
 

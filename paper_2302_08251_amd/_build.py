@@ -23,8 +23,18 @@ def _hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src):
+def _deps_mtime():
+    """Newest modification time of the headers every translation unit may include."""
+    heads = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+    heads.append(os.path.join(os.path.dirname(HERE), "include", "llama_mi.h"))
+    return max(os.path.getmtime(h) for h in heads)
+
+
+def _compile(src, incremental=False, deps=0.0):
     obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
+    if incremental and os.path.exists(obj):
+        if os.path.getmtime(obj) >= max(deps, os.path.getmtime(os.path.join(CSRC, src))):
+            return obj
     cmd = [_hipcc()] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
@@ -33,11 +43,14 @@ def _compile(src):
     return obj
 
 
-def build(verbose=False, jobs=None):
+def build(verbose=False, jobs=None, incremental=False):
+    """Compiles every source (incremental=True: only those older than their
+    source or any header) and links the library."""
     os.makedirs(OBJ, exist_ok=True)
     jobs = jobs or min(len(SOURCES), os.cpu_count() or 4, 16)
+    deps = _deps_mtime()
     with ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda f: _compile(f, incremental, deps), SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [_hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -50,5 +63,5 @@ def build(verbose=False, jobs=None):
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)
     sys.exit(0)

@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cstdio>
 #include <fstream>
+#include <functional>
 #include <sstream>
 
 #include "batch.hpp"
@@ -197,12 +198,24 @@ std::string device_key(const llama_batch* b) {
   for (auto& ch : arch)
     if (ch == '"' || ch == '\\') ch = '_';
   uint64_t recs = 0, h = 1469598103934665603ull;
+  auto mix = [&](uint64_t x) { h = (h ^ x) * 1099511628211ull; };
+  // every descriptor field that changes a plan: kinds, lanes, flags, code
+  // widths and storage types down the inner chain, leaf types, index type
+  std::function<void(const MapDesc&)> mix_map = [&](const MapDesc& m) {
+    mix(((uint64_t)m.kind << 48) ^ ((uint64_t)m.lanes << 16) ^ m.flags);
+    mix(((uint64_t)m.bits << 32) ^ ((uint64_t)m.exp_bits << 16) ^ m.man_bits);
+    for (auto t : m.stored) mix(0x100 + (uint64_t)t);
+    if (m.inner) mix_map(*m.inner);
+    if (m.inner2) mix_map(*m.inner2);
+    mix(0xFFFF);
+  };
   for (size_t v = 0; v < b->srcs.size(); ++v) {
     recs += b->srcs[v]->n;
-    uint64_t x = (uint64_t)b->srcs[v]->map.kind * 131 + b->dsts[v]->map.kind * 7 + b->srcs[v]->map.lanes * 1009 +
-                 b->dsts[v]->map.lanes * 9176 + (b->srcs[v]->map.inner ? 3 : 0) + (b->dsts[v]->map.inner ? 5 : 0) +
-                 b->srcs[v]->n * 31 + b->srcs[v]->rec.size();
-    h = (h ^ x) * 1099511628211ull;
+    mix(b->srcs[v]->n);
+    for (auto t : b->srcs[v]->rec) mix(0x200 + (uint64_t)t);
+    mix_map(b->srcs[v]->map);
+    mix_map(b->dsts[v]->map);
+    mix(((uint64_t)b->srcs[v]->index_type << 8) | (uint64_t)b->dsts[v]->index_type);
   }
   char buf[256];
   std::snprintf(buf, sizeof(buf), "%s|cu%d|views%zu|records%llu|shape%016llx", arch.c_str(), cus, b->srcs.size(),
@@ -332,7 +345,19 @@ llama_status llama_batch_create(uint32_t n, const llama_view* const* srcs, llama
   const std::string key = device_key(b.get());
   uint32_t T = 0, G = 0, P = 0;
   llama_status st;
-  if (!(tune_cache && cache_lookup(tune_cache, key, T, G, P))) {
+  const bool cached = tune_cache && cache_lookup(tune_cache, key, T, G, P);
+  // a cached entry whose tile sizes no longer plan for these views (for
+  // example a tile that does not fit the LDS of wider leaves) is tuned anew
+  bool usable = cached;
+  if (cached) {
+    std::vector<BatchItem> items;
+    std::vector<uint32_t> prefix;
+    std::vector<Plan> pv;
+    uint32_t lds = 0;
+    usable = build_items(b.get(), T, items, prefix, lds) == LLAMA_OK && per_view_plans(b.get(), P, pv) == LLAMA_OK;
+    clear_error();
+  }
+  if (!usable) {
     const auto t0 = std::chrono::steady_clock::now();
     if ((st = autotune(b.get(), granule, T, G, P)) != LLAMA_OK) {
       release_device(b.get());

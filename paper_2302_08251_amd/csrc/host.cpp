@@ -947,7 +947,8 @@ static llama_status plan_views(const llama_view* src, const llama_view* dst, con
     return LLAMA_OK;
   }
   const bool ssplit = src->map.kind == LLAMA_MAP_SPLIT, dsplit = dst->map.kind == LLAMA_MAP_SPLIT;
-  if (dst->map.kind == LLAMA_MAP_NULL) return LLAMA_OK;
+  // A SPLIT source is divided before a NULL destination drops the values:
+  // an instrumented part still counts the loads of its fields (Sec. 4).
   if (ssplit || dsplit) {
     const uint32_t k = ssplit ? src->map.lanes : dst->map.lanes;
     for (int part = 0; part < 2; ++part) {
@@ -960,6 +961,7 @@ static llama_status plan_views(const llama_view* src, const llama_view* dst, con
     }
     return LLAMA_OK;
   }
+  if (dst->map.kind == LLAMA_MAP_NULL) return LLAMA_OK;
   CopyStep step;
   llama_status s = src->map.kind == LLAMA_MAP_NULL ? plan_zero(dst, step.plan) : plan_copy(src, dst, params, step.plan);
   if (s != LLAMA_OK) return s;

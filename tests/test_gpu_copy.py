@@ -95,10 +95,40 @@ def test_index_types_give_same_result():
     planes = bits_planes(n, F32x7, seed=4)
     src_host = oracle.store_planes(F32x7, CFG2["aos"], planes)
     exp = oracle.copy(F32x7, CFG2["aos"], src_host, CFG2["aosoa32"], n, fill=0xA5)
-    for idx in ("i16", "u16", "i32", "u32", "u64"):
-        if idx.endswith("16") and n * 28 > 32767:
-            continue
+    for idx in ("i32", "u32", "i64", "u64"):
         sv = gpu_view(F32x7, CFG2["aos"], n, src_host, index=idx)
         dv = gpu_view(F32x7, CFG2["aosoa32"], n, fill=0xA5, index=idx)
         lm.llama_copy(sv, dv)
         assert_blobs_equal(download(dv), exp, idx)
+
+
+# 16-bit index types (Sec. 2): the largest ragged record counts whose every
+# blob still fits the type.  7 x f32 records are 28 bytes; an AoSoA-64 blob
+# of ceil(n / 64) * 64 records must stay below 2^15 (I16) or 2^16 (U16) bytes.
+IDX16 = {"i16": 1150, "u16": 2303}
+
+
+@pytest.mark.parametrize("idx", sorted(IDX16))
+def test_index16_all_pairs(idx):
+    n = IDX16[idx]
+    limit = 0x7FFF if idx == "i16" else 0xFFFF
+    assert -(-n // 64) * 64 * 28 - 1 <= limit
+    planes = bits_planes(n, F32x7, seed=5)
+    for a, sa in CFG2.items():
+        src_host = oracle.store_planes(F32x7, sa, planes)
+        sv = gpu_view(F32x7, sa, n, src_host, index=idx)
+        for b, sb in CFG2.items():
+            say("index", idx, a, b, n)
+            exp = oracle.copy(F32x7, sa, src_host, sb, n, fill=0xA5)
+            dv = gpu_view(F32x7, sb, n, fill=0xA5, index=idx)
+            lm.llama_copy(sv, dv)
+            assert_blobs_equal(download(dv), exp, "%s %s -> %s" % (idx, a, b))
+
+
+def test_index16_rejects_what_does_not_fit():
+    with pytest.raises(lm.LlamaError) as e:
+        lm.View(F32x7, CFG2["aos"], [1171], index_type="i16")
+    assert e.value.name == "INDEX_OVERFLOW"
+    with pytest.raises(lm.LlamaError) as e:
+        lm.View(F32x7, CFG2["aosoa64"], [2305], index_type="u16")
+    assert e.value.name == "INDEX_OVERFLOW"

@@ -183,6 +183,15 @@ def test_instrumented_parts_and_null(n):
     lm.llama_copy(v2, lm.View(F32x7, null, [n]))
     oracle.copy(F32x7, fs, s2, null, n, dst_blobs=[])
     assert_blobs_equal(download(v2), s2, "loads into null")
+    # a Split source with instrumented parts counts its loads into Null too
+    s4 = oracle.store_planes(F32x7, a, planes, fill=0)
+    for i in (1, 6, 7, 8, 9):
+        s4[i][:] = 0
+    v4 = view(F32x7, a, n, s4)
+    lm.llama_copy(v4, lm.View(F32x7, null, [n]))
+    oracle.copy(F32x7, a, s4, null, n, dst_blobs=[])
+    assert any(b.any() for b in (s4[1], s4[6])), "the oracle counts the loads"
+    assert_blobs_equal(download(v4), s4, "split loads into null")
     hd = heat({"kind": "aosoa", "lanes": 3}, 8)
     d3 = host_blobs(F32x7, hd, n)
     v3 = view(F32x7, hd, n, d3)
