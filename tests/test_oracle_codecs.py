@@ -494,3 +494,89 @@ def test_float_rne_view_copy_uses_the_flag():
     assert np.array_equal(packed[0], stream)
     trunc = oracle.copy(["f32"], {"kind": "soa_mb"}, blobs, {"kind": "bitpack_float", "exp": 5, "man": 10}, n)
     assert not np.array_equal(packed[0], trunc[0])
+
+
+# ---------------------------------------------------------------- BitPackedFloat from f64 sources
+
+def encode_trunc_reference(x, E, M):
+    """Truncation from any binary64 value: the largest-magnitude code whose exact value is
+    <= |x|, Inf when the exponent exceeds the bias (exact rationals, bisection over the
+    monotone positive codes)."""
+    f = float(x)
+    sign = 1 if np.signbit(f) else 0
+    ax = abs(Fraction(f))
+    bias = (1 << (E - 1)) - 1
+    inf_code = ((1 << E) - 1) << M
+    if ax >= Fraction(2) ** (bias + 1):
+        return inf_code | (sign << (E + M))
+    lo, hi = 0, inf_code - 1
+    while lo < hi:
+        mid = (lo + hi + 1) // 2
+        if decode_exact(mid, E, M) <= ax:
+            lo = mid
+        else:
+            hi = mid - 1
+    return lo | (sign << (E + M))
+
+
+def probe_values64(E, M, rng):
+    """binary64 probes: target-format edges and their f64 neighbours, f64 subnormals,
+    random finite bit patterns and values near 1 in magnitude."""
+    bias = (1 << (E - 1)) - 1
+    vals = [0.0, -0.0, 1.0, -1.0, 0.1, -2.5e-3, 1e300, -1e-300, 5e-324, -2.2250738585072014e-308]
+    maxfin = (2 - Fraction(1, 1 << M)) * Fraction(2) ** bias
+    edges = [maxfin, Fraction(2) ** (bias + 1), Fraction(2) ** (1 - bias), Fraction(2) ** (1 - bias - M)]
+    edges += [edges[3] / 2, edges[3] * 3 / 2, edges[2] * 3 / 4]
+    for e in edges:
+        v = float(e) if e < Fraction(2) ** 1024 else None
+        if v is None or v == 0.0:
+            continue
+        vals += [v, float(np.nextafter(v, 0.0)), float(np.nextafter(v, np.inf))]
+        # halfway between two neighbouring codes near the edge (RNE ties)
+    for c in rng.integers(0, ((1 << E) - 1) << M, 30):
+        c = int(c)
+        a = decode_exact(c, E, M)
+        b = decode_exact(c + 1, E, M) if c + 1 < ((1 << E) - 1) << M else Fraction(2) ** (bias + 1)
+        mid = (a + b) / 2
+        if Fraction(float(mid)) == mid:
+            vals += [float(mid), -float(mid), float(a), float(np.nextafter(float(mid), 0.0))]
+    rb = rng.integers(0, 2 ** 63, 60, dtype=np.uint64) | (rng.integers(0, 2, 60, dtype=np.uint64) << np.uint64(63))
+    rb = rb[(rb & np.uint64(0x7FF0000000000000)) != np.uint64(0x7FF0000000000000)]
+    vals += [float(x) for x in rb.view(np.float64)]
+    vals += [float(x) for x in rng.standard_normal(20)]
+    subn = rng.integers(1, 1 << 52, 10, dtype=np.uint64)
+    vals += [float(x) for x in subn.view(np.float64)]
+    return vals
+
+
+F64_FORMATS = [(11, 20), (11, 0), (9, 22), (2, 29), (8, 15), (5, 10)]
+
+
+@pytest.mark.parametrize("E,M", F64_FORMATS)
+def test_float_encode_from_f64_brute_force_both_roundings(E, M):
+    rng = np.random.default_rng(1000 + 31 * E + M)
+    vals = np.array(probe_values64(E, M, rng), dtype=np.float64)
+    got_t = oracle.float_encode_array(vals, "f64", E, M).astype(np.int64).tolist()
+    got_r = oracle.float_encode_array(vals, "f64", E, M, rne=True).astype(np.int64).tolist()
+    for v, gt, gr in zip(vals.tolist(), got_t, got_r):
+        assert gt == encode_trunc_reference(v, E, M), ("trunc", E, M, v.hex())
+        assert gr == encode_rne_reference(v, E, M), ("rne", E, M, v.hex())
+
+
+@pytest.mark.parametrize("E,M", F64_FORMATS)
+def test_float_encode_from_f64_specials(E, M):
+    """Inf keeps its sign; a NaN keeps its sign and top M payload bits with the quiet
+    bit forced (M = 0: Inf); both roundings agree on them."""
+    inf_code = ((1 << E) - 1) << M
+    sgn = 1 << (E + M)
+    payloads = [1, 1 << 51, (1 << 52) - 1, 0x5555555555555, 0x0000000ABCDEF]
+    bits = [0x7FF0000000000000, 0xFFF0000000000000]
+    bits += [0x7FF0000000000000 | p for p in payloads] + [0xFFF0000000000000 | p for p in payloads]
+    x = np.array(bits, dtype=np.uint64).view(np.float64)
+    for rne in (False, True):
+        got = oracle.float_encode_array(x, "f64", E, M, rne=rne).astype(np.int64).tolist()
+        assert got[0] == inf_code and got[1] == inf_code | sgn
+        for k, p in enumerate(payloads):
+            quiet = (1 << (M - 1)) if M else 0
+            want = inf_code | quiet | ((p >> (52 - M)) & ((1 << M) - 1))
+            assert got[2 + k] == want and got[2 + len(payloads) + k] == want | sgn, (rne, hex(p))
