@@ -297,6 +297,21 @@ llama_status llama_batch_destroy(llama_batch* batch);
 llama_status nbody_step(llama_view* particles, uint32_t steps, float dt, float eps2,
                         void* stream);
 
+/* nbody_step for callers that cannot allocate device memory: code under
+ * hipGraph stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same kernels, arguments and results as nbody_step (bit for
+ * bit), but no library allocation on any call: the per-slice partial
+ * accelerations live in a static device array of 16 MiB that each GPU the
+ * library runs on holds until the process ends.  That array fits at most
+ * 1398101 particles (12 bytes of partial sums per particle once a view has
+ * 2^19 particles or more); a larger view returns LLAMA_ERR_NO_MEMORY and
+ * nothing is enqueued.  Every call on one GPU shares that GPU's array and
+ * writes every element it reads, so nothing needs clearing between calls;
+ * calls that overlap in time on one GPU (other streams, other threads) race
+ * on it and must be serialised by the caller.  Errors as for nbody_step. */
+llama_status nbody_step_noalloc(llama_view* particles, uint32_t steps, float dt, float eps2,
+                                void* stream);
+
 /* Total energy  E = 1/2 sum_i m_i |v_i|^2 - sum_{i<j} m_i m_j (|x_i-x_j|^2+eps2)^(-1/2)
  * computed on the GPU in FP64 with a fixed reduction order (deterministic),
  * from the values as decoded through the mapping.  Blocks until the result

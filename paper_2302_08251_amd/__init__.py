@@ -24,7 +24,7 @@ __all__ = [
     "llama_mapping_blob_count", "llama_mapping_blob_size", "llama_view_create",
     "llama_view_destroy", "llama_view_records", "llama_copy", "llama_copy_ex", "llama_pack",
     "llama_unpack", "llama_batch_create", "llama_batch_launch", "llama_batch_launch_per_view",
-    "llama_batch_get_info", "llama_batch_destroy", "nbody_step", "nbody_energy",
+    "llama_batch_get_info", "llama_batch_destroy", "nbody_step", "nbody_step_noalloc", "nbody_energy",
     "llama_last_error", "llama_version", "SCALARS", "KINDS", "INDEX_TYPES",
 ]
 
@@ -102,6 +102,7 @@ def lib():
         "llama_batch_get_info": [vp, P(BatchInfo)],
         "llama_batch_destroy": [vp],
         "nbody_step": [vp, u32, C.c_float, C.c_float, vp],
+        "nbody_step_noalloc": [vp, u32, C.c_float, C.c_float, vp],
         "nbody_energy": [vp, C.c_float, P(C.c_double), vp],
     }
     for name, args in sig.items():
@@ -293,6 +294,10 @@ def llama_batch_destroy(batch):
 
 def nbody_step(view, steps, dt, eps2, stream=None):
     _check(lib().nbody_step(_h(view), steps, dt, eps2, _stream(stream)))
+
+
+def nbody_step_noalloc(view, steps, dt, eps2, stream=None):
+    _check(lib().nbody_step_noalloc(_h(view), steps, dt, eps2, _stream(stream)))
 
 
 def nbody_energy(view, eps2, stream=None):

@@ -282,6 +282,33 @@ struct Scratch {
 
 Scratch g_scratch[64];
 
+// Scratch of the allocation-free step (nbody_step_noalloc): the per-slice
+// partial accelerations live in this file-scope device array instead of a
+// library allocation.  Each GPU holds its own copy at its own address, which
+// hipGetSymbolAddress returns once per device with that device current; the
+// host code only ever passes that address to kernels, never the array's name.
+constexpr size_t kStaticScratchBytes = 16u << 20;
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+struct StaticScratch {
+  std::once_flag once;
+  hipError_t err = hipSuccess;
+  void* ptr = nullptr;
+};
+
+StaticScratch g_static[64];
+
+llama_status static_scratch_get(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return fail(LLAMA_ERR_HIP, "hipGetDevice failed");
+  StaticScratch& sc = g_static[dev];
+  std::call_once(sc.once, [&sc]() { sc.err = hipGetSymbolAddress(&sc.ptr, HIP_SYMBOL(scratch)); });
+  if (sc.err != hipSuccess || !sc.ptr)
+    return fail(LLAMA_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(sc.err));
+  *out = sc.ptr;
+  return LLAMA_OK;
+}
+
 llama_status scratch_get(size_t bytes, hipStream_t st, void** out, double** host) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return fail(LLAMA_ERR_HIP, "hipGetDevice failed");
@@ -333,6 +360,34 @@ uint32_t nb_slices(uint32_t n) {
   return sl;
 }
 
+// Bytes of per-slice partial accelerations for n particles.
+size_t nb_scratch_bytes(uint32_t n) { return (size_t)nb_slices(n) * 3u * n * sizeof(float); }
+
+// Largest particle count whose partial accelerations fit the static scratch
+// (for n >= 2^19 one slice, 12 bytes per particle).
+constexpr uint32_t kNoallocMaxParticles = (uint32_t)(kStaticScratchBytes / 12u);
+
+// The launches of `steps` update + move steps, partial sums in `part`
+// (nb_scratch_bytes(n) bytes; every element read is written first).
+llama_status nb_launch_steps(const Side& s, uint32_t n, uint32_t steps, float dt, float eps2, float* part,
+                             hipStream_t st) {
+  const uint32_t slices = nb_slices(n);
+  uint32_t per = (n + slices - 1) / slices;
+  per = (per + NB_T - 1) / NB_T * NB_T;
+  const uint32_t iblocks = (n + NB_T - 1) / NB_T;
+  const uint32_t used = (n + per - 1) / per;
+  for (uint32_t k = 0; k < steps; ++k) {
+    hipLaunchKernelGGL(k_nb_update, dim3(iblocks, used), dim3(NB_T), 0, st, s, n, eps2, per, part);
+    if (s.layout == LY_STREAM)
+      hipLaunchKernelGGL(k_nb_kick_drift_stream, dim3(iblocks), dim3(NB_T), 0, st, s, n, dt, used, part);
+    else
+      hipLaunchKernelGGL(k_nb_kick_drift, dim3(iblocks), dim3(NB_T), 0, st, s, n, dt, used, part);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(LLAMA_ERR_HIP, std::string("n-body launch: ") + hipGetErrorString(e));
+  return LLAMA_OK;
+}
+
 }  // namespace
 }  // namespace lm
 
@@ -349,24 +404,28 @@ llama_status nbody_step(llama_view* view, uint32_t steps, float dt, float eps2, 
   const uint32_t n = (uint32_t)view->n;
   if (n == 0 || steps == 0) return LLAMA_OK;
   hipStream_t st = (hipStream_t)stream;
-  const uint32_t slices = nb_slices(n);
-  uint32_t per = (n + slices - 1) / slices;
-  per = (per + NB_T - 1) / NB_T * NB_T;
-  void* scratch;
-  if ((r = scratch_get((size_t)slices * 3u * n * sizeof(float), st, &scratch, nullptr)) != LLAMA_OK) return r;
-  float* part = (float*)scratch;
-  const uint32_t iblocks = (n + NB_T - 1) / NB_T;
-  const uint32_t used = (n + per - 1) / per;
-  for (uint32_t k = 0; k < steps; ++k) {
-    hipLaunchKernelGGL(k_nb_update, dim3(iblocks, used), dim3(NB_T), 0, st, s, n, eps2, per, part);
-    if (s.layout == LY_STREAM)
-      hipLaunchKernelGGL(k_nb_kick_drift_stream, dim3(iblocks), dim3(NB_T), 0, st, s, n, dt, used, part);
-    else
-      hipLaunchKernelGGL(k_nb_kick_drift, dim3(iblocks), dim3(NB_T), 0, st, s, n, dt, used, part);
-  }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return fail(LLAMA_ERR_HIP, std::string("n-body launch: ") + hipGetErrorString(e));
-  return LLAMA_OK;
+  void* buf;
+  if ((r = scratch_get(nb_scratch_bytes(n), st, &buf, nullptr)) != LLAMA_OK) return r;
+  return nb_launch_steps(s, n, steps, dt, eps2, (float*)buf, st);
+}
+
+llama_status nbody_step_noalloc(llama_view* view, uint32_t steps, float dt, float eps2, void* stream) {
+  clear_error();
+  Side s;
+  llama_status r = nb_side(view, s);
+  if (r != LLAMA_OK) return r;
+  if (!(eps2 > 0.f)) return fail(LLAMA_ERR_INVALID_ARG, "eps2 must be > 0");
+  const uint32_t n = (uint32_t)view->n;
+  const size_t need = nb_scratch_bytes(n);
+  if (need > kStaticScratchBytes)
+    return fail(LLAMA_ERR_NO_MEMORY, "nbody_step_noalloc: " + std::to_string(n) + " particles need " +
+                                         std::to_string(need) + " bytes of scratch, the static maximum is " +
+                                         std::to_string(kStaticScratchBytes) + " (at most " +
+                                         std::to_string(kNoallocMaxParticles) + " particles)");
+  if (n == 0 || steps == 0) return LLAMA_OK;
+  void* buf;
+  if ((r = static_scratch_get(&buf)) != LLAMA_OK) return r;
+  return nb_launch_steps(s, n, steps, dt, eps2, (float*)buf, (hipStream_t)stream);
 }
 
 llama_status nbody_energy(const llama_view* view, float eps2, double* energy, void* stream) {
@@ -381,14 +440,14 @@ llama_status nbody_energy(const llama_view* view, float eps2, double* energy, vo
   const size_t dbytes = (size_t)7 * n * sizeof(double);
   const size_t pbytes = (size_t)nb * nb * sizeof(double);
   const size_t kbytes = (size_t)nb * sizeof(double);
-  void* scratch;
+  void* buf;
   double* host;
-  if ((r = scratch_get(dbytes + pbytes + kbytes + 64, st, &scratch, &host)) != LLAMA_OK) return r;
+  if ((r = scratch_get(dbytes + pbytes + kbytes + 64, st, &buf, &host)) != LLAMA_OK) return r;
   if (n == 0) {
     *energy = 0.0;
     return LLAMA_OK;
   }
-  double* d = (double*)scratch;
+  double* d = (double*)buf;
   double* pot = d + (size_t)7 * n;
   double* kin = pot + (size_t)nb * nb;
   double* out = kin + nb;
