@@ -524,11 +524,19 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     if (mode == RM_SPLIT) return (uint64_t)F * ES * (t + 16u);
     return 0;
   };
+  // A Bytesplit source merged into an AoS destination is merged in place over
+  // the source image when every thread can hold its (quad, field) items in
+  // registers: one LDS image instead of two.
+  const bool merge_aos = canonical && mode == RM_MERGE && D.layout == LY_AOS;
+  auto in_place = [&](uint64_t t) {
+    return merge_aos && (t / 4u) * F <= (uint64_t)merge_in_place_items(ES) * kThreads;
+  };
   // pack: the tile's stream-word image (t * B / 8 bytes per field)
   const bool pack = plan.kind == PK_PACK;
   auto lds_total = [&](uint64_t t) -> uint64_t {
     const uint64_t a = tile_lds_bytes(S, (uint32_t)t);
     if (pack) return ((a + 15u) & ~15ull) + (uint64_t)D.ncols * (t * D.bits / 8u);
+    if (in_place(t)) return a;
     return canonical ? ((a + 15u) & ~15ull) + can_bytes(t) : a;
   };
   const uint64_t gran = tile_granule(S, D);
@@ -555,6 +563,7 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
                             : unpack ? 8192
                             : plan.kind == PK_CONV ? 32768  // ChangeType: 32 KiB on the wider side
                             : aos2aos ? 7168
+                            : merge_aos ? 16384  // one image, merged in place
                             : canonical ? 32768
                             : (bs && bd) ? 24576
                             : (bs || bd) ? 30720
@@ -569,6 +578,18 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
       while (gran * (k + 1) <= 65536 && lds_total(gran * (k + 1)) <= lds_cap &&
              gran * (k + 1) * dst_bytes <= 65536)
         ++k;
+    }
+    // Byte planes (a planar Bytesplit side) move in whole 1 KiB wave groups
+    // when a tile has 1024 or 512 records.  Measured best: 1024 when both
+    // sides are byte planes and for the in-place merge into AoS, 512 for the
+    // fused split and merge.
+    if (plan.kind == PK_RAW && !lds_cap && (bs || bd)) {
+      const uint64_t want = ((bs && bd) || merge_aos) ? 1024 : 512;
+      uint64_t kp = std::max<uint64_t>(1, want / gran);
+      while (kp > 1 && (lds_total(gran * kp) > kMaxTileLds || (merge_aos && !in_place(gran * kp)) ||
+                        gran * kp * dst_bytes > 65536))
+        --kp;
+      if (!merge_aos || in_place(gran * kp)) k = kp;
     }
     tile = gran * k;
   }
@@ -603,7 +624,8 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
       g.rec_bytes = F * ES;
       g.lanes = 1;
       g.div_L = make_div(F);  // the relayout's (quad, field) split
-      plan.args.can_off = (uint32_t)((tile_lds_bytes(S, (uint32_t)tile) + 15u) & ~15u);
+      // offset 0: merged in place over the source image
+      plan.args.can_off = in_place(tile) ? 0u : (uint32_t)((tile_lds_bytes(S, (uint32_t)tile) + 15u) & ~15u);
     } else if (canonical) {
       plan.args.colrun = runs(D);
       g.layout = LY_PLANAR;

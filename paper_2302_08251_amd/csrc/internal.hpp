@@ -20,6 +20,10 @@ constexpr uint32_t kMaxFields = 64;
 constexpr uint32_t kMaxCols = 64;
 constexpr uint32_t kThreads = 256;            // threads per workgroup of the tile kernels
 constexpr uint32_t kMaxTileLds = 64 * 1024;   // LDS bytes per tile
+// Items (4 records x 1 field) per thread that the in-place merge of a
+// Bytesplit source into an AoS image holds in registers, by leaf bytes.
+template <int ES> constexpr int kMergeInPlaceItems = ES == 8 ? 4 : 8;
+inline uint32_t merge_in_place_items(uint32_t es) { return es == 8 ? 4u : 8u; }
 
 enum Layout : uint32_t { LY_AOS = 0, LY_PLANAR = 1, LY_AOSOA = 2, LY_STREAM = 3 };
 

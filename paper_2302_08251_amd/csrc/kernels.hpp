@@ -30,69 +30,64 @@ enum RawVariant : uint32_t {
   RV_MERGE_FUSED = 5,  // RV_MERGE without the canonical image
 };
 
-// Phase B for one destination layout DL from an LDS image whose layout is
-// chosen by a wave-uniform branch.
-template <int U, int DL, int COLRUN, typename G>
+// Phase B for one destination layout DL from an LDS image of layout SL.
+template <int U, int DL, int SL, int COLRUN, typename G>
 __device__ __forceinline__ void phase_b_dl(const G& s, const Side& d, uint64_t i0, uint32_t nt, const uint8_t* lds) {
-  if constexpr (COLRUN) {
-    if constexpr (DL == LY_AOS) {
-      store_identity<U>(s, d, i0, nt, lds);  // AoS image of the same record: identical bytes
-    } else {
-      if (s.layout == LY_AOSOA) store_colrun<U, DL, LY_AOSOA>(s, d, i0, nt, lds);
-      else store_colrun<U, DL, LY_PLANAR>(s, d, i0, nt, lds);
-    }
+  if constexpr (COLRUN && DL == LY_AOS) {
+    store_identity<U>(s, d, i0, nt, lds);  // AoS image of the same record: identical bytes
+  } else if constexpr (COLRUN && SL != LY_AOS) {
+    store_colrun<U, DL, SL>(s, d, i0, nt, lds);
   } else {
-    switch (s.layout) {
-      case LY_AOS: store_raw<U, DL, LY_AOS>(s, d, i0, nt, lds); break;
-      case LY_PLANAR: store_raw<U, DL, LY_PLANAR>(s, d, i0, nt, lds); break;
-      default: store_raw<U, DL, LY_AOSOA>(s, d, i0, nt, lds); break;
-    }
+    store_raw<U, DL, SL>(s, d, i0, nt, lds);
   }
 }
 
-// One tile of a raw copy of records whose leaves are ES bytes: verbatim
-// source image, an optional relayout through a canonical planar image when
-// exactly one side is a Bytesplit, then Phase B.
-template <int ES, int RV, int DL, int COLRUN>
-__device__ __forceinline__ void tile_raw(const TileArgs& a, uint64_t i0, uint32_t nt, uint8_t* lds) {
-  load_tile(a.src, i0, nt, lds);
+// One tile of a raw copy of records whose leaves are ES bytes, from a source
+// of layout SL: verbatim source image, an optional relayout through a
+// canonical planar image when exactly one side is a Bytesplit, then Phase B.
+template <int ES, int RV, int DL, int COLRUN, int SL>
+__device__ __forceinline__ void tile_raw_sl(const TileArgs& a, uint64_t i0, uint32_t nt, uint8_t* lds) {
+  load_tile<SL>(a.src, i0, nt, lds);
   wait_tile_loads();
   if constexpr (RV == RV_SPLIT_FUSED) {
-    if (DL == LY_AOSOA && (a.dst.lanes & 15u)) {  // runs of 4 records only
-      switch (a.src.layout) {
-        case LY_PLANAR: store_split_fused<ES, LY_PLANAR, DL>(a.src, a.dst, i0, nt, lds); break;
-        case LY_AOSOA: store_split_fused<ES, LY_AOSOA, DL>(a.src, a.dst, i0, nt, lds); break;
-        default: store_split_fused<ES, LY_AOS, DL>(a.src, a.dst, i0, nt, lds); break;
-      }
-    } else {
-      switch (a.src.layout) {
-        case LY_PLANAR: store_split_fused16<ES, LY_PLANAR, DL>(a.src, a.dst, i0, nt, lds); break;
-        case LY_AOSOA: store_split_fused16<ES, LY_AOSOA, DL>(a.src, a.dst, i0, nt, lds); break;
-        default: store_split_fused16<ES, LY_AOS, DL>(a.src, a.dst, i0, nt, lds); break;
-      }
-    }
+    if (DL == LY_AOSOA && (a.dst.lanes & 15u)) store_split_fused<ES, SL, DL>(a.src, a.dst, i0, nt, lds);  // runs of 4 records
+    else store_split_fused16<ES, SL, DL>(a.src, a.dst, i0, nt, lds);
   } else if constexpr (RV == RV_MERGE_FUSED) {
-    if (a.src.layout == LY_AOSOA) store_merge_fused<ES, LY_AOSOA, DL>(a.src, a.dst, i0, nt, lds);
-    else store_merge_fused<ES, LY_PLANAR, DL>(a.src, a.dst, i0, nt, lds);
+    store_merge_fused<ES, SL, DL>(a.src, a.dst, i0, nt, lds);
   } else if constexpr (RV == RV_MERGE || RV == RV_SPLIT) {
     uint8_t* can = lds + a.can_off;
     if constexpr (RV == RV_MERGE && DL == LY_AOS) {
-      if (a.src.layout == LY_AOSOA) relayout_merge_aos<ES, LY_AOSOA>(a.src, nt, lds, can, a.can);
-      else relayout_merge_aos<ES, LY_PLANAR>(a.src, nt, lds, can, a.can);
+      if (a.can_off == 0u) relayout_merge_aos_inplace<ES, SL, kMergeInPlaceItems<ES>>(a.src, nt, lds, a.can);
+      else relayout_merge_aos<ES, SL>(a.src, nt, lds, can, a.can);
     } else if constexpr (RV == RV_MERGE) {
-      if (a.src.layout == LY_AOSOA) relayout_merge<ES, LY_AOSOA>(a.src, nt, lds, can, a.can);
-      else relayout_merge<ES, LY_PLANAR>(a.src, nt, lds, can, a.can);
+      relayout_merge<ES, SL>(a.src, nt, lds, can, a.can);
     } else {
-      switch (a.src.layout) {
-        case LY_PLANAR: relayout_split<ES, LY_PLANAR>(a.src, nt, lds, can, a.can); break;
-        case LY_AOSOA: relayout_split<ES, LY_AOSOA>(a.src, nt, lds, can, a.can); break;
-        default: relayout_split<ES, LY_AOS>(a.src, nt, lds, can, a.can); break;
-      }
+      relayout_split<ES, SL>(a.src, nt, lds, can, a.can);
     }
     __syncthreads();
-    phase_b_dl<RV == RV_MERGE ? ES : 1, DL, COLRUN>(a.can, a.dst, i0, nt, can);
+    // the canonical image: the destination's AoS record image (merge into
+    // AoS) or planes of elements (merge) or bytes (split)
+    constexpr int CL = (RV == RV_MERGE && DL == LY_AOS) ? LY_AOS : LY_PLANAR;
+    phase_b_dl<RV == RV_MERGE ? ES : 1, DL, CL, COLRUN>(a.can, a.dst, i0, nt, can);
   } else {
-    phase_b_dl<RV == RV_DIRECT_ES ? ES : 1, DL, COLRUN>(a.src, a.dst, i0, nt, lds);
+    phase_b_dl<RV == RV_DIRECT_ES ? ES : 1, DL, SL, COLRUN>(a.src, a.dst, i0, nt, lds);
+  }
+}
+
+// The source layouts a variant can meet: a Bytesplit source (the merges)
+// keeps byte columns in planes or AoSoA blocks; every other variant takes
+// any physical layout.
+template <int ES, int RV, int DL, int COLRUN>
+__device__ __forceinline__ void tile_raw(const TileArgs& a, uint64_t i0, uint32_t nt, uint8_t* lds) {
+  if constexpr (RV == RV_MERGE || RV == RV_MERGE_FUSED) {
+    if (a.src.layout == LY_AOSOA) tile_raw_sl<ES, RV, DL, COLRUN, LY_AOSOA>(a, i0, nt, lds);
+    else tile_raw_sl<ES, RV, DL, COLRUN, LY_PLANAR>(a, i0, nt, lds);
+  } else {
+    switch (a.src.layout) {
+      case LY_AOS: tile_raw_sl<ES, RV, DL, COLRUN, LY_AOS>(a, i0, nt, lds); break;
+      case LY_PLANAR: tile_raw_sl<ES, RV, DL, COLRUN, LY_PLANAR>(a, i0, nt, lds); break;
+      default: tile_raw_sl<ES, RV, DL, COLRUN, LY_AOSOA>(a, i0, nt, lds); break;
+    }
   }
 }
 
@@ -136,13 +131,13 @@ __device__ __forceinline__ void phase_b_conv(const Side& s, const Side& d, uint6
 #undef LM_CALL
 }
 
-template <int CODEC>
+template <int CODEC, int FMT>
 __device__ __forceinline__ void phase_b_pack(const Side& s, const Side& d, uint64_t i0, uint32_t nt,
                                              const uint8_t* lds, uint32_t* words, uint32_t wstride) {
   switch (s.layout) {
-    case LY_AOS: store_pack<CODEC, LY_AOS>(s, d, i0, nt, lds, words, wstride); break;
-    case LY_PLANAR: store_pack<CODEC, LY_PLANAR>(s, d, i0, nt, lds, words, wstride); break;
-    default: store_pack<CODEC, LY_AOSOA>(s, d, i0, nt, lds, words, wstride); break;
+    case LY_AOS: store_pack<CODEC, FMT, LY_AOS>(s, d, i0, nt, lds, words, wstride); break;
+    case LY_PLANAR: store_pack<CODEC, FMT, LY_PLANAR>(s, d, i0, nt, lds, words, wstride); break;
+    default: store_pack<CODEC, FMT, LY_AOSOA>(s, d, i0, nt, lds, words, wstride); break;
   }
 }
 
@@ -170,7 +165,9 @@ __global__ __launch_bounds__(kThreads) void k_raw(const TileArgs a) {
   }
 }
 
-// kind: 1 conversion, 2 pack, 3 unpack
+// kind: 1 conversion, 2 pack, 3 unpack.  P0: the conversion (Conv) or the
+// codec (Codec); U: the destination unit in bytes (conversion, unpack) or the
+// compile-time float format (pack, PackFmt).
 template <int KIND, int P0, int U>
 __global__ __launch_bounds__(kThreads) void k_tile(const TileArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
@@ -183,10 +180,11 @@ __global__ __launch_bounds__(kThreads) void k_tile(const TileArgs a) {
     uint32_t* words = (uint32_t*)(lds + a.can_off);
     const uint32_t wstride = (a.tile * a.dst.bits) >> 5;
     if constexpr (KIND == 2) pack_clear_words(words, a.dst.ncols * wstride);
-    load_tile(a.src, i0, nt, lds);
+    if constexpr (KIND == 3) load_tile<LY_STREAM>(a.src, i0, nt, lds);
+    else load_tile(a.src, i0, nt, lds);
     wait_tile_loads();
     if constexpr (KIND == 1) phase_b_conv<P0, U>(a.src, a.dst, i0, nt, lds);
-    else if constexpr (KIND == 2) phase_b_pack<P0>(a.src, a.dst, i0, nt, lds, words, wstride);
+    else if constexpr (KIND == 2) phase_b_pack<P0, U>(a.src, a.dst, i0, nt, lds, words, wstride);
     else phase_b_unpack<P0, U>(a.src, a.dst, i0, nt, lds);
     __syncthreads();
   }

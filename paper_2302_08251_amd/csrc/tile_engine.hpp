@@ -24,6 +24,7 @@ namespace lm {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
 typedef __attribute__((address_space(3))) void lds_void;
 
 constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit format, gfx9 family
@@ -53,8 +54,17 @@ struct SegGeo {
   uint32_t len;   // bytes per segment (equal for all segments)
 };
 
+// The segment helpers take the side's layout as a template argument when
+// the caller knows it (L >= 0), so that no layout switch is left in the item
+// loops; L = -1 reads it from the side.
+template <int L>
+__device__ __forceinline__ uint32_t layout_of(const Side& s) {
+  return L >= 0 ? (uint32_t)L : s.layout;
+}
+
+template <int L = -1>
 __device__ __forceinline__ SegGeo seg_geo(const Side& s, uint32_t nt) {
-  switch (s.layout) {
+  switch (layout_of<L>(s)) {
     case LY_AOS: return {1u, nt * s.rec_bytes};
     case LY_AOSOA: return {1u, fdiv(nt + s.lanes - 1, s.div_L) * s.lanes * s.rec_bytes};
     case LY_PLANAR: return {s.ncols, nt * s.cs};
@@ -63,8 +73,9 @@ __device__ __forceinline__ SegGeo seg_geo(const Side& s, uint32_t nt) {
 }
 
 // Byte offset, within its blob, where segment `seg` of the tile at i0 starts.
+template <int L = -1>
 __device__ __forceinline__ uint64_t seg_start(const Side& s, uint32_t seg, uint64_t i0) {
-  switch (s.layout) {
+  switch (layout_of<L>(s)) {
     case LY_AOS:
     case LY_AOSOA: return i0 * s.rec_bytes;
     case LY_PLANAR: return (s.mb ? 0ull : s.n * s.cs * seg) + i0 * s.cs;
@@ -72,16 +83,20 @@ __device__ __forceinline__ uint64_t seg_start(const Side& s, uint32_t seg, uint6
   }
 }
 
+template <int L = -1>
 __device__ __forceinline__ const void* seg_blob(const Side& s, uint32_t seg) {
-  const bool per_col = s.layout == LY_STREAM || (s.layout == LY_PLANAR && s.mb);
+  const uint32_t l = layout_of<L>(s);
+  const bool per_col = l == LY_STREAM || (l == LY_PLANAR && s.mb);
   return per_col ? s.blob[seg] : s.blob[0];
 }
 
 // LDS offset of segment `seg`'s allocation.  The data starts at
 // seg_lds + (start mod 16), so a 16-byte aligned global chunk lands on a
 // 16-byte aligned LDS chunk.
+template <int L = -1>
 __device__ __forceinline__ uint32_t seg_lds(const Side& s, uint32_t seg) {
-  return (s.layout == LY_PLANAR || s.layout == LY_STREAM) ? seg * s.lds_stride : 0u;
+  const uint32_t l = layout_of<L>(s);
+  return (l == LY_PLANAR || l == LY_STREAM) ? seg * s.lds_stride : 0u;
 }
 
 // Start phase (mod 16) of planar column c of a single-blob side.
@@ -90,32 +105,47 @@ __device__ __forceinline__ uint32_t planar_phase(const G& s, uint32_t c) {
   return s.mb ? 0u : ((s.n_mod16 * s.cs * c) & 15u);
 }
 
+// Divisor for a run-time d >= 1 built on the device once per tile (one
+// 32-bit division), so that the item loops split an item index into
+// (segment, group) with one multiply-high: fdiv(x, div) = x / d exactly
+// while x * d < 2^32, which every item loop below satisfies.
+__device__ __forceinline__ Div make_div_dev(uint32_t d) {
+  Div r;
+  r.d = d;
+  r.pow2 = (d & (d - 1u)) == 0u ? 1u : 0u;
+  r.sh = r.pow2 ? (uint32_t)__builtin_ctz(d) : 0u;
+  r.m = r.pow2 ? 0u : 0xFFFFFFFFu / d + 1u;
+  return r;
+}
+
 // ---------------------------------------------------------------------------
 // Phase A: source tile -> LDS, verbatim
 // ---------------------------------------------------------------------------
 
+template <int L = -1>
 __device__ __forceinline__ void load_tile(const Side& s, uint64_t i0, uint32_t nt, uint8_t* lds) {
-  const SegGeo g = seg_geo(s, nt);
+  const SegGeo g = seg_geo<L>(s, nt);
   const uint32_t w = wave_id(), nw = num_waves(), lane = lane_id();
   const uint32_t gps = (g.len + 15u + 1023u) >> 10;  // groups of 64 chunks per segment
+  const Div dg = make_div_dev(gps);
   const uint32_t items = g.nseg * gps;
   for (uint32_t it = w; it < items; it += nw) {
-    const uint32_t seg = it / gps;
+    const uint32_t seg = fdiv(it, dg);
     const uint32_t grp = it - seg * gps;
-    const uint64_t start = seg_start(s, seg, i0);
+    const uint64_t start = seg_start<L>(s, seg, i0);
     const uint32_t phase = (uint32_t)start & 15u;
     const uint64_t abase = start - phase;
-    const auto rs = make_rsrc((const uint8_t*)seg_blob(s, seg) + abase, s.blob_size - abase);
+    const auto rs = make_rsrc((const uint8_t*)seg_blob<L>(s, seg) + abase, s.blob_size - abase);
     const uint32_t chunk = grp * 64u + lane;
     if (chunk * 16u < phase + g.len) {
       if (abase + chunk * 16ull + 16ull <= s.blob_size) {
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void*)(lds + seg_lds(s, seg) + grp * 1024u),
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void*)(lds + seg_lds<L>(s, seg) + grp * 1024u),
                                                  16, chunk * 16u, 0, 0, 0);
       } else {
         // The chunk crosses the end of the blob.  Buffer range checks work on
         // whole dwords, so a blob size that is not a multiple of 4 would zero
         // the last bytes: fetch this chunk byte by byte instead.
-        uint8_t* out = lds + seg_lds(s, seg) + chunk * 16u;
+        uint8_t* out = lds + seg_lds<L>(s, seg) + chunk * 16u;
         const uint64_t left = s.blob_size - (abase + chunk * 16ull);
         for (uint32_t k = 0; k < 16u && k < left; ++k)
           out[k] = __builtin_amdgcn_raw_buffer_load_b8(rs, chunk * 16u + k, 0, 0);
@@ -234,19 +264,20 @@ __device__ __forceinline__ void put_unit(uint32_t (&w)[4], int t, uint64_t v) {
 // one group of 64 chunks per wave at a time; `body(rs, seg, chunk, x0, len)`
 // handles one chunk whose first byte is segment byte x0 (negative for the
 // bytes before a misaligned segment start).
-template <typename Body>
+template <int L = -1, typename Body>
 __device__ __forceinline__ void for_dst_chunks(const Side& d, uint64_t i0, uint32_t nt, Body&& body) {
-  const SegGeo g = seg_geo(d, nt);
+  const SegGeo g = seg_geo<L>(d, nt);
   const uint32_t w = wave_id(), nw = num_waves(), lane = lane_id();
   const uint32_t gps = (g.len + 15u + 1023u) >> 10;
+  const Div dg = make_div_dev(gps);
   const uint32_t items = g.nseg * gps;
   for (uint32_t it = w; it < items; it += nw) {
-    const uint32_t seg = it / gps;
+    const uint32_t seg = fdiv(it, dg);
     const uint32_t grp = it - seg * gps;
-    const uint64_t start = seg_start(d, seg, i0);
+    const uint64_t start = seg_start<L>(d, seg, i0);
     const uint32_t phase = (uint32_t)start & 15u;
     const uint64_t abase = start - phase;
-    const auto rs = make_rsrc((const uint8_t*)seg_blob(d, seg) + abase, d.blob_size - abase);
+    const auto rs = make_rsrc((const uint8_t*)seg_blob<L>(d, seg) + abase, d.blob_size - abase);
     const uint32_t chunk = grp * 64u + lane;
     const int x0 = (int)(chunk * 16u) - (int)phase;
     if (x0 < (int)g.len) body(rs, seg, chunk * 16u, x0, g.len);
@@ -374,9 +405,10 @@ __device__ __forceinline__ void relayout_merge(const Side& s, uint32_t nt, const
                                                const Geo& cg) {
   const uint32_t F = s.ncols / ES;
   const uint32_t quads = (nt + 3u) >> 2;
+  const Div dq = make_div_dev(quads);
   const uint32_t items = F * quads;
   for (uint32_t q = threadIdx.x; q < items; q += blockDim.x) {
-    const uint32_t f = q / quads;
+    const uint32_t f = fdiv(q, dq);
     const uint32_t r = (q - f * quads) * 4u;
     const uint32_t a = f * cg.lds_stride + planar_phase(cg, f) + r * ES;
     uint32_t out[ES];  // the 4 elements, as ES dwords in memory order
@@ -405,9 +437,10 @@ __device__ __forceinline__ void relayout_split(const Side& s, uint32_t nt, const
                                                const Geo& cg) {
   const uint32_t F = s.ncols;
   const uint32_t quads = (nt + 3u) >> 2;
+  const Div dq = make_div_dev(quads);
   const uint32_t items = F * quads;
   for (uint32_t q = threadIdx.x; q < items; q += blockDim.x) {
-    const uint32_t f = q / quads;
+    const uint32_t f = fdiv(q, dq);
     const uint32_t r = (q - f * quads) * 4u;
     uint32_t e[ES];
     read_elems4<ES, SL>(s, lds, r, f, e);
@@ -484,6 +517,59 @@ __device__ __forceinline__ void relayout_merge_aos(const Side& s, uint32_t nt, c
   }
 }
 
+// The same merge into the AoS record image, in place over the source image:
+// every thread first reads and transposes all its (quad, field) items into
+// registers (at most MAXI), then, after a barrier, writes them over the byte
+// planes.  The tile then needs one LDS image instead of two, which lets more
+// workgroups share a CU.  The host picks this form (canonical image offset
+// 0) when quads * fields <= MAXI * threads.
+template <int ES, int SL, int MAXI>
+__device__ __forceinline__ void relayout_merge_aos_inplace(const Side& s, uint32_t nt, uint8_t* lds, const Geo& cg) {
+  const uint32_t F = cg.ncols;
+  const uint32_t items = ((nt + 3u) >> 2) * F;
+  uint32_t out[MAXI][ES];  // per item: the 4 elements, as ES dwords in memory order
+#pragma unroll
+  for (int k = 0; k < MAXI; ++k) {
+    const uint32_t it = threadIdx.x + (uint32_t)k * blockDim.x;
+    if (it >= items) break;
+    const uint32_t q = fdiv(it, cg.div_L);  // div_L holds the field count here
+    const uint32_t f = it - q * F;
+    const uint32_t r = 4u * q;
+    if constexpr (ES == 2) {
+      const uint32_t b0 = read_run4<SL>(s, lds, r, 2 * f), b1 = read_run4<SL>(s, lds, r, 2 * f + 1);
+      out[k][0] = __builtin_amdgcn_perm(b1, b0, 0x05010400u);
+      out[k][1] = __builtin_amdgcn_perm(b1, b0, 0x07030602u);
+    } else {
+      constexpr int DW = ES / 4;
+#pragma unroll
+      for (int h = 0; h < DW; ++h) {
+        uint32_t in[4], o[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) in[c] = read_run4<SL>(s, lds, r, f * ES + 4 * h + c);
+        transpose4x4(in, o);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) out[k][j * DW + h] = o[j];
+      }
+    }
+  }
+  __syncthreads();  // every byte plane is read before any record is written over it
+#pragma unroll
+  for (int k = 0; k < MAXI; ++k) {
+    const uint32_t it = threadIdx.x + (uint32_t)k * blockDim.x;
+    if (it >= items) break;
+    const uint32_t q = fdiv(it, cg.div_L);
+    const uint32_t f = it - q * F;
+    uint8_t* base = lds + 4u * q * cg.rec_bytes + f * ES;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      uint8_t* e = base + j * cg.rec_bytes;
+      if constexpr (ES == 2) *(uint16_t*)e = (uint16_t)(out[k][j >> 1] >> (16 * (j & 1)));
+      else if constexpr (ES == 4) *(uint32_t*)e = out[k][j];
+      else *(u32x2*)e = u32x2{out[k][2 * j], out[k][2 * j + 1]};
+    }
+  }
+}
+
 template <int U, int DL, int SL, typename G>
 __device__ __forceinline__ void raw_chunk(const G& s, const Side& d, uint32_t nt, const uint8_t* lds,
                                           __amdgpu_buffer_rsrc_t rs, uint32_t seg, uint32_t off, int x0,
@@ -508,7 +594,7 @@ __device__ __forceinline__ void raw_chunk(const G& s, const Side& d, uint32_t nt
 template <int U, int DL, int SL, typename G>
 __device__ __forceinline__ void store_raw(const G& s, const Side& d, uint64_t i0, uint32_t nt,
                                           const uint8_t* lds) {
-  for_dst_chunks(d, i0, nt, [&](__amdgpu_buffer_rsrc_t rs, uint32_t seg, uint32_t off, int x0, uint32_t len) {
+  for_dst_chunks<DL>(d, i0, nt, [&](__amdgpu_buffer_rsrc_t rs, uint32_t seg, uint32_t off, int x0, uint32_t len) {
     raw_chunk<U, DL, SL>(s, d, nt, lds, rs, seg, off, x0, len);
   });
 }
@@ -517,7 +603,7 @@ template <int U, int DL, int SL, typename G>
 __device__ __forceinline__ void store_colrun(const G& s, const Side& d, uint64_t i0, uint32_t nt,
                                              const uint8_t* lds) {
   constexpr uint32_t NREC = 16 / U;
-  for_dst_chunks(d, i0, nt, [&](__amdgpu_buffer_rsrc_t rs, uint32_t seg, uint32_t off, int x0, uint32_t len) {
+  for_dst_chunks<DL>(d, i0, nt, [&](__amdgpu_buffer_rsrc_t rs, uint32_t seg, uint32_t off, int x0, uint32_t len) {
     if (x0 >= 0 && x0 + 16 <= (int)len) {
       uint32_t r, b;
       dst_inv<DL>(d, seg, (uint32_t)x0, r, b);
@@ -555,7 +641,7 @@ __device__ __forceinline__ void store_colrun(const G& s, const Side& d, uint64_t
 template <int U, typename G>
 __device__ __forceinline__ void store_identity(const G& s, const Side& d, uint64_t i0, uint32_t nt,
                                                const uint8_t* lds) {
-  for_dst_chunks(d, i0, nt, [&](__amdgpu_buffer_rsrc_t rs, uint32_t seg, uint32_t off, int x0, uint32_t len) {
+  for_dst_chunks<LY_AOS>(d, i0, nt, [&](__amdgpu_buffer_rsrc_t rs, uint32_t seg, uint32_t off, int x0, uint32_t len) {
     if (x0 + 16 <= (int)len) __builtin_amdgcn_raw_buffer_store_b128(*(const u32x4*)(lds + x0), rs, off, 0, kStoreNT);
     else raw_chunk<U, LY_AOS, LY_AOS>(s, d, nt, lds, rs, seg, off, x0, len);
   });
@@ -609,10 +695,11 @@ __device__ __forceinline__ void store_split_fused(const Side& s, const Side& d, 
   const bool shifted = DL == LY_PLANAR && !d.mb && (d.n & 3u);
   const uint32_t per = shifted ? 63u : 64u;
   const uint32_t gpf = (quads + per - 1u) / per;
-  const uint32_t items = F * gpf;
   const uint32_t w0 = wave_id(), nw = num_waves(), lane = lane_id();
+  const Div dg = make_div_dev(gpf);
+  const uint32_t items = F * gpf;
   for (uint32_t it = w0; it < items; it += nw) {
-    const uint32_t f = it / gpf;
+    const uint32_t f = fdiv(it, dg);
     const int qi = (int)((it - f * gpf) * per + lane) - (shifted ? 1 : 0);
     // every lane takes part (the cross-lane read below needs its neighbour);
     // lanes outside the tile read record 0 and store nothing
@@ -715,10 +802,11 @@ __device__ __forceinline__ void store_split_fused16(const Side& s, const Side& d
   const bool shifted = DL == LY_PLANAR && !d.mb && (d.n & 15u);
   const uint32_t per = shifted ? 63u : 64u;
   const uint32_t gpf = (runs + per - 1u) / per;
-  const uint32_t items = F * gpf;
   const uint32_t w0 = wave_id(), nw = num_waves(), lane = lane_id();
+  const Div dg = make_div_dev(gpf);
+  const uint32_t items = F * gpf;
   for (uint32_t it = w0; it < items; it += nw) {
-    const uint32_t f = it / gpf;
+    const uint32_t f = fdiv(it, dg);
     const int qi = (int)((it - f * gpf) * per + lane) - (shifted ? 1 : 0);
     const bool act = qi >= 0 && qi < (int)runs;
     const uint32_t q = act ? (uint32_t)qi : 0u;
@@ -796,10 +884,11 @@ __device__ __forceinline__ void store_merge_fused(const Side& s, const Side& d, 
   const uint32_t F = d.ncols;
   const uint32_t quads = (nt + 3u) >> 2;
   const uint32_t gpf = (quads + 63u) >> 6;
-  const uint32_t items = F * gpf;
   const uint32_t w0 = wave_id(), nw = num_waves(), lane = lane_id();
+  const Div dg = make_div_dev(gpf);
+  const uint32_t items = F * gpf;
   for (uint32_t it = w0; it < items; it += nw) {
-    const uint32_t f = it / gpf;
+    const uint32_t f = fdiv(it, dg);
     const uint32_t q = (it - f * gpf) * 64u + lane;
     const void* blob = (DL == LY_PLANAR && d.mb) ? d.blob[f] : d.blob[0];
     const uint64_t cb = col_base<DL>(d, i0, f);
@@ -1169,12 +1258,29 @@ struct ConvInfo {
                                                                                                      : 2;
 };
 
+// f32 -> f16 and f32 -> bf16 with the hardware conversions (v_cvt_f16_f32,
+// v_cvt_pk_bf16_f32): both round to nearest even under the kernel's FP mode,
+// which keeps denormals, and overflow to Inf.  A NaN is rewritten with the
+// ChangeType rule: sign, top payload bits, quiet bit set.
+__device__ __forceinline__ uint32_t cvt_f32_f16(uint32_t x) {
+  const uint32_t h = __builtin_bit_cast(uint16_t, (_Float16)__builtin_bit_cast(float, x));
+  const bool nan = (x & 0x7FFFFFFFu) > 0x7F800000u;
+  const uint32_t hn = ((x >> 16) & 0x8000u) | 0x7E00u | ((x >> 13) & 0x3FFu);
+  return nan ? hn : h;
+}
+
+__device__ __forceinline__ uint32_t cvt_f32_bf16(uint32_t x) {
+  const uint32_t h = __builtin_bit_cast(uint16_t, (__bf16)__builtin_bit_cast(float, x));
+  const bool nan = (x & 0x7FFFFFFFu) > 0x7F800000u;
+  return nan ? ((x >> 16) | 0x40u) : h;
+}
+
 template <int CONV>
 __device__ __forceinline__ uint64_t convert(uint64_t v) {
   if constexpr (CONV == CV_F64_F32) return cvt_f64_f32(v);
   else if constexpr (CONV == CV_F32_F64) return cvt_f32_f64((uint32_t)v);
-  else if constexpr (CONV == CV_F32_F16) return narrow_rne<8, 23, 5, 10>(v);
-  else if constexpr (CONV == CV_F32_BF16) return narrow_rne<8, 23, 8, 7>(v);
+  else if constexpr (CONV == CV_F32_F16) return cvt_f32_f16((uint32_t)v);
+  else if constexpr (CONV == CV_F32_BF16) return cvt_f32_bf16((uint32_t)v);
   else if constexpr (CONV == CV_F64_F16) return narrow_rne<11, 52, 5, 10>(v);
   else if constexpr (CONV == CV_F64_BF16) return narrow_rne<11, 52, 8, 7>(v);
   else if constexpr (CONV == CV_F16_F32) return widen<5, 10, 8, 23>(v);
@@ -1193,8 +1299,8 @@ __device__ __forceinline__ void store_conv_planar(const Side& s, const Side& d, 
   constexpr int V = 16 / ESD;         // values per destination chunk
   constexpr int NB = V * ESS;         // source bytes per chunk: 4 .. 64
   const uint32_t chunks = (nt + V - 1u) / V;
-  const uint64_t start = seg_start(d, f, i0);
-  const auto rs = make_rsrc((const uint8_t*)seg_blob(d, f) + start, d.blob_size - start);
+  const uint64_t start = seg_start<LY_PLANAR>(d, f, i0);
+  const auto rs = make_rsrc((const uint8_t*)seg_blob<LY_PLANAR>(d, f) + start, d.blob_size - start);
   const uint8_t* plane = lds + f * s.lds_stride;
   for (uint32_t c = threadIdx.x; c < chunks; c += blockDim.x) {
     const uint32_t r = c * V;
@@ -1244,7 +1350,7 @@ __device__ __forceinline__ void store_conv(const Side& s, const Side& d, uint64_
   constexpr uint32_t FULL = (1u << NU) - 1u;
   constexpr int ESS = ConvInfo<CONV>::ES_SRC, ESD = ConvInfo<CONV>::ES_DST;
   constexpr int LOG_ESD = ESD == 8 ? 3 : ESD == 4 ? 2 : 1;
-  for_dst_chunks(d, i0, nt, [&](__amdgpu_buffer_rsrc_t rs, uint32_t seg, uint32_t off, int x0, uint32_t len) {
+  for_dst_chunks<DL>(d, i0, nt, [&](__amdgpu_buffer_rsrc_t rs, uint32_t seg, uint32_t off, int x0, uint32_t len) {
     uint32_t w[4] = {0u, 0u, 0u, 0u};
     uint32_t valid = 0;
 #pragma unroll
@@ -1267,11 +1373,50 @@ __device__ __forceinline__ void store_conv(const Side& s, const Side& d, uint64_
 
 // ---------------------------------------------------------------------------
 // Phase B, pack into bit streams (Sec. 3 bit-packed SoA).  Every value of the
-// tile is encoded exactly once and its code ORed into an LDS image of the
-// tile's stream words with LDS atomics (a code spans at most two words).
-// The image starts zeroed, so the bits past the last value stay zero, and
-// goes out with 16-byte stores: a wave writes 1 KiB contiguous per store.
+// tile is encoded exactly once.  A lane takes four consecutive values of an
+// element plane (one 16-byte LDS read) and writes their codes into an LDS
+// image of the tile's stream words: with B = 8, 16 or 32 the four codes fill
+// whole words of their own, which are stored plainly; otherwise the codes
+// (as one group for B <= 8, two pairs for B <= 16, singly above) are ORed in
+// with LDS atomics, since a word's bits may come from two lanes.  The image
+// starts zeroed, so the bits past the last value stay zero, and goes out with
+// 16-byte stores: a wave writes 1 KiB contiguous per store.
 // ---------------------------------------------------------------------------
+
+// Float formats that get a compile-time encoder (any other goes through the
+// run-time one).
+enum PackFmt : uint32_t { PF_RUNTIME = 0, PF_E8M7 = 1, PF_E5M10 = 2, PF_E8M15 = 3 };
+
+template <int FMT> struct PackFmtInfo { static constexpr uint32_t E = 0, M = 0; };
+template <> struct PackFmtInfo<PF_E8M7> { static constexpr uint32_t E = 8, M = 7; };
+template <> struct PackFmtInfo<PF_E5M10> { static constexpr uint32_t E = 5, M = 10; };
+template <> struct PackFmtInfo<PF_E8M15> { static constexpr uint32_t E = 8, M = 15; };
+
+// Truncating f32 encoder for a format fixed at compile time.  With E = 8 the
+// target has the source's exponent range, so normals, subnormals and Inf
+// keep their exponent field and lose their low mantissa bits: one shift, and
+// a NaN keeps its all-ones exponent and gets its quiet bit.  Other formats
+// constant-fold the run-time encoder.
+template <uint32_t E, uint32_t M>
+__device__ __forceinline__ uint32_t enc_f32_fixed(uint32_t x) {
+  if constexpr (E == 8) {
+    const uint32_t ax = x & 0x7FFFFFFFu;
+    uint32_t c = ax >> (23u - M);
+    if constexpr (M > 0) c |= ax > 0x7F800000u ? (1u << (M - 1u)) : 0u;
+    return c | ((x >> 31) << (E + M));
+  } else {
+    return enc_f32(x, E, M);
+  }
+}
+
+template <int CODEC, int FMT>
+__device__ __forceinline__ uint32_t encode_fmt(uint64_t v, const Side& d) {
+  if constexpr (CODEC == CD_F32 && FMT != PF_RUNTIME)
+    return enc_f32_fixed<PackFmtInfo<FMT>::E, PackFmtInfo<FMT>::M>((uint32_t)v);
+  else
+    return encode<CODEC>(v, d);
+}
+
 __device__ __forceinline__ void pack_clear_words(uint32_t* words, uint32_t nwords) {
   for (uint32_t k = threadIdx.x * 4u; k < nwords; k += blockDim.x * 4u) *(u32x4*)(words + k) = u32x4{0u, 0u, 0u, 0u};
 }
@@ -1285,19 +1430,74 @@ __device__ __forceinline__ void or_bits(uint32_t* wf, uint32_t bit, uint32_t cod
     __hip_atomic_fetch_or(wf + w + 1u, code >> (32u - sh), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-template <int CODEC, int SL>
+template <int CODEC, int FMT, int SL>
 __device__ __forceinline__ void store_pack(const Side& s, const Side& d, uint64_t i0, uint32_t nt,
                                            const uint8_t* lds, uint32_t* words, uint32_t wstride) {
   constexpr int ES = CodecInfo<CODEC>::ES;
   const uint32_t B = d.bits;
   const uint32_t F = d.ncols;
+  const uint32_t nw = (nt * B + 31u) >> 5;  // stream words of this tile
+  // element planes of 4-byte values on the 16-byte grid (not Bytesplit byte
+  // planes) are read four values at a time; with B a multiple of 8 their
+  // codes bypass the word image
+  auto quad_plane = [&](uint32_t f) {
+    return SL == LY_PLANAR && ES == 4 && s.cs == 4u && (planar_phase(s, f) & 15u) == 0u;
+  };
+  auto direct = [&](uint32_t f) { return quad_plane(f) && (B & 7u) == 0u; };
+  bool imaged = false;  // some field went through the word image
   for (uint32_t f = 0; f < F; ++f) {
     uint32_t* wf = words + f * wstride;
     if constexpr (SL == LY_PLANAR && ES == 4) {
-      if (s.cs == 4u && (planar_phase(s, f) & 15u) == 0u) {  // element planes (not Bytesplit byte planes)
-        // four consecutive values per lane from one 16-byte LDS read; their
-        // codes go in as one group (B <= 8), two pairs (B <= 16) or singly,
-        // which cuts the atomics and the lanes that meet on one word
+      if (direct(f)) {
+        // B = 8, 16, 24, 32: the four codes of a quad are B / 8 whole words
+        // starting on a word boundary, so they go from registers straight to
+        // the stream (a wave writes 64 * B / 2 contiguous bytes per store, whole
+        // 128-byte lines); no word image, no barrier.  Only the tile's last
+        // quad may hold words past the stream, which are dropped word by word.
+        const uint8_t* plane = lds + f * s.lds_stride;
+        const uint32_t quads = (nt + 3u) >> 2;
+        const uint64_t start = seg_start<LY_STREAM>(d, f, i0);
+        const auto rs = make_rsrc((const uint8_t*)seg_blob<LY_STREAM>(d, f) + start, d.blob_size - start);
+        const uint32_t wq = B >> 3;  // words per quad
+        for (uint32_t q = threadIdx.x; q < quads; q += blockDim.x) {
+          const u32x4 v = *(const u32x4*)(plane + 16u * q);
+          const uint32_t r = 4u * q;
+          uint32_t c[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) c[k] = encode_fmt<CODEC, FMT>(v[k], d);
+          if (r + 4u > nt) {
+#pragma unroll
+            for (int k = 1; k < 4; ++k) c[k] = r + k < nt ? c[k] : 0u;
+          }
+          // every word starts defined: the branches below fill 1 to 4 of them
+          uint32_t w[4] = {0u, 0u, 0u, 0u};
+          if (B == 8u) {
+            w[0] = c[0] | (c[1] << 8) | (c[2] << 16) | (c[3] << 24);
+          } else if (B == 16u) {
+            w[0] = c[0] | (c[1] << 16);
+            w[1] = c[2] | (c[3] << 16);
+          } else if (B == 24u) {
+            w[0] = c[0] | (c[1] << 24);
+            w[1] = (c[1] >> 8) | (c[2] << 16);
+            w[2] = (c[2] >> 16) | (c[3] << 8);
+          } else {
+            w[0] = c[0]; w[1] = c[1]; w[2] = c[2]; w[3] = c[3];
+          }
+          const uint32_t off = 4u * wq * q;
+          if (wq * q + wq <= nw) {
+            if (B == 8u) __builtin_amdgcn_raw_buffer_store_b32(w[0], rs, off, 0, kStoreNT);
+            else if (B == 16u) __builtin_amdgcn_raw_buffer_store_b64(u32x2{w[0], w[1]}, rs, off, 0, kStoreNT);
+            else if (B == 24u) __builtin_amdgcn_raw_buffer_store_b96(u32x3{w[0], w[1], w[2]}, rs, off, 0, kStoreNT);
+            else __builtin_amdgcn_raw_buffer_store_b128(u32x4{w[0], w[1], w[2], w[3]}, rs, off, 0, kStoreNT);
+          } else {
+            for (uint32_t k = 0; k < wq && wq * q + k < nw; ++k)
+              __builtin_amdgcn_raw_buffer_store_b32(w[k], rs, off + 4u * k, 0, 0);
+          }
+        }
+        continue;
+      }
+      if (quad_plane(f)) {
+        imaged = true;
         const uint8_t* plane = lds + f * s.lds_stride;
         const uint32_t quads = (nt + 3u) >> 2;
         for (uint32_t q = threadIdx.x; q < quads; q += blockDim.x) {
@@ -1305,34 +1505,45 @@ __device__ __forceinline__ void store_pack(const Side& s, const Side& d, uint64_
           const uint32_t r = 4u * q;
           uint32_t c[4];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {  // branch-free: values past the tile give code 0
-            const uint32_t keep = 0u - (uint32_t)(r + k < nt);
-            c[k] = encode<CODEC>(v[k], d) & keep;
-          }
-          const uint32_t bit = r * B;
-          if (B <= 8u) {
-            or_bits(wf, bit, c[0] | (c[1] << B) | (c[2] << (2u * B)) | (c[3] << (3u * B)), 4u * B);
-          } else if (B <= 16u) {
-            or_bits(wf, bit, c[0] | (c[1] << B), 2u * B);
-            or_bits(wf, bit + 2u * B, c[2] | (c[3] << B), 2u * B);
-          } else {
+          for (int k = 0; k < 4; ++k) c[k] = encode_fmt<CODEC, FMT>(v[k], d);
+          if (r + 4u > nt) {  // the tile's last, partial quad: values past the tile give code 0
 #pragma unroll
-            for (int k = 0; k < 4; ++k) or_bits(wf, bit + k * B, c[k], B);
+            for (int k = 1; k < 4; ++k) c[k] = r + k < nt ? c[k] : 0u;
+          }
+          if (B == 8u) {
+            wf[q] = c[0] | (c[1] << 8) | (c[2] << 16) | (c[3] << 24);
+          } else if (B == 16u) {
+            *(u32x2*)(wf + 2u * q) = u32x2{c[0] | (c[1] << 16), c[2] | (c[3] << 16)};
+          } else if (B == 32u) {
+            *(u32x4*)(wf + 4u * q) = u32x4{c[0], c[1], c[2], c[3]};
+          } else {
+            const uint32_t bit = r * B;
+            if (B < 8u) {
+              or_bits(wf, bit, c[0] | (c[1] << B) | (c[2] << (2u * B)) | (c[3] << (3u * B)), 4u * B);
+            } else if (B < 16u) {
+              or_bits(wf, bit, c[0] | (c[1] << B), 2u * B);
+              or_bits(wf, bit + 2u * B, c[2] | (c[3] << B), 2u * B);
+            } else {
+#pragma unroll
+              for (int k = 0; k < 4; ++k) or_bits(wf, bit + k * B, c[k], B);
+            }
           }
         }
         continue;
       }
     }
+    imaged = true;
     for (uint32_t r = threadIdx.x; r < nt; r += blockDim.x)
-      or_bits(wf, r * B, encode<CODEC>(fetch_elem<ES, SL>(s, lds, r, f), d), B);
+      or_bits(wf, r * B, encode_fmt<CODEC, FMT>(fetch_elem<ES, SL>(s, lds, r, f), d), B);
   }
+  if (!imaged) return;  // block-uniform: every field went out directly
   __syncthreads();
-  const uint32_t nw = (nt * B + 31u) >> 5;  // stream words of this tile
   const uint32_t nch = (nw + 3u) >> 2;
   for (uint32_t f = 0; f < F; ++f) {
+    if (direct(f)) continue;
     // tiles are multiples of 128 records, so every tile's stream starts 16-byte aligned
-    const uint64_t start = seg_start(d, f, i0);
-    const auto rs = make_rsrc((const uint8_t*)seg_blob(d, f) + start, d.blob_size - start);
+    const uint64_t start = seg_start<LY_STREAM>(d, f, i0);
+    const auto rs = make_rsrc((const uint8_t*)seg_blob<LY_STREAM>(d, f) + start, d.blob_size - start);
     const uint32_t* wf = words + f * wstride;
     for (uint32_t c = threadIdx.x; c < nch; c += blockDim.x) {
       const u32x4 v = *(const u32x4*)(wf + 4u * c);
@@ -1361,8 +1572,8 @@ __device__ __forceinline__ void store_unpack_planar4(const Side& s, const Side& 
                                                      const uint8_t* lds, uint32_t f) {
   const uint32_t B = s.bits;
   const uint32_t quads = (nt + 3u) >> 2;
-  const uint64_t start = seg_start(d, f, i0);
-  const auto rs = make_rsrc((const uint8_t*)seg_blob(d, f) + start, d.blob_size - start);
+  const uint64_t start = seg_start<LY_PLANAR>(d, f, i0);
+  const auto rs = make_rsrc((const uint8_t*)seg_blob<LY_PLANAR>(d, f) + start, d.blob_size - start);
   const uint8_t* plane = lds + f * s.lds_stride;
   for (uint32_t q = threadIdx.x; q < quads; q += blockDim.x) {
     const uint32_t r = 4u * q;
@@ -1393,7 +1604,7 @@ __device__ __forceinline__ void store_unpack(const Side& s, const Side& d, uint6
   constexpr int ES = CodecInfo<CODEC>::ES;
   constexpr int LOG_ES = ES == 8 ? 3 : ES == 4 ? 2 : ES == 2 ? 1 : 0;
   const uint32_t B = s.bits;
-  for_dst_chunks(d, i0, nt, [&](__amdgpu_buffer_rsrc_t rs, uint32_t seg, uint32_t off, int x0, uint32_t len) {
+  for_dst_chunks<DL>(d, i0, nt, [&](__amdgpu_buffer_rsrc_t rs, uint32_t seg, uint32_t off, int x0, uint32_t len) {
     uint32_t w[4] = {0u, 0u, 0u, 0u};
     uint32_t valid = 0;
 #pragma unroll
