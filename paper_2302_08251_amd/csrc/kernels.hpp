@@ -30,15 +30,16 @@ enum RawVariant : uint32_t {
   RV_MERGE_FUSED = 5,  // RV_MERGE without the canonical image
 };
 
-// Phase B for one destination layout DL from an LDS image of layout SL.
-template <int U, int DL, int SL, int COLRUN, typename G>
+// Phase B for one destination layout DL from an LDS image of layout SL, with
+// the item loop form FORM (see load_tile).
+template <int U, int DL, int SL, int COLRUN, int FORM, typename G>
 __device__ __forceinline__ void phase_b_dl(const G& s, const Side& d, uint64_t i0, uint32_t nt, const uint8_t* lds) {
   if constexpr (COLRUN && DL == LY_AOS) {
-    store_identity<U>(s, d, i0, nt, lds);  // AoS image of the same record: identical bytes
+    store_identity<U, FORM>(s, d, i0, nt, lds);  // AoS image of the same record: identical bytes
   } else if constexpr (COLRUN && SL != LY_AOS) {
-    store_colrun<U, DL, SL>(s, d, i0, nt, lds);
+    store_colrun<U, DL, SL, FORM>(s, d, i0, nt, lds);
   } else {
-    store_raw<U, DL, SL>(s, d, i0, nt, lds);
+    store_raw<U, DL, SL, FORM>(s, d, i0, nt, lds);
   }
 }
 
@@ -47,7 +48,11 @@ __device__ __forceinline__ void phase_b_dl(const G& s, const Side& d, uint64_t i
 // canonical planar image when exactly one side is a Bytesplit, then Phase B.
 template <int ES, int RV, int DL, int COLRUN, int SL>
 __device__ __forceinline__ void tile_raw_sl(const TileArgs& a, uint64_t i0, uint32_t nt, uint8_t* lds) {
-  load_tile<SL>(a.src, i0, nt, lds);
+  // loop forms (measured): element copies take the run-time-layout loops in
+  // Phase B, and in Phase A when the source is one segment (AoS, AoSoA)
+  constexpr int FORM_A = RV == RV_DIRECT_ES && (SL == LY_AOS || SL == LY_AOSOA) ? 1 : 0;
+  constexpr int FORM_B = RV == RV_DIRECT_ES ? 1 : 0;
+  load_tile<SL, FORM_A>(a.src, i0, nt, lds);
   wait_tile_loads();
   if constexpr (RV == RV_SPLIT_FUSED) {
     if (DL == LY_AOSOA && (a.dst.lanes & 15u)) store_split_fused<ES, SL, DL>(a.src, a.dst, i0, nt, lds);  // runs of 4 records
@@ -68,9 +73,9 @@ __device__ __forceinline__ void tile_raw_sl(const TileArgs& a, uint64_t i0, uint
     // the canonical image: the destination's AoS record image (merge into
     // AoS) or planes of elements (merge) or bytes (split)
     constexpr int CL = (RV == RV_MERGE && DL == LY_AOS) ? LY_AOS : LY_PLANAR;
-    phase_b_dl<RV == RV_MERGE ? ES : 1, DL, CL, COLRUN>(a.can, a.dst, i0, nt, can);
+    phase_b_dl<RV == RV_MERGE ? ES : 1, DL, CL, COLRUN, 0>(a.can, a.dst, i0, nt, can);
   } else {
-    phase_b_dl<RV == RV_DIRECT_ES ? ES : 1, DL, SL, COLRUN>(a.src, a.dst, i0, nt, lds);
+    phase_b_dl<RV == RV_DIRECT_ES ? ES : 1, DL, SL, COLRUN, FORM_B>(a.src, a.dst, i0, nt, lds);
   }
 }
 
