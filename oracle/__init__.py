@@ -66,6 +66,10 @@ def lib():
         L.orc_store.argtypes = [P(_Rec), P(_Map), u64, C.c_void_p, u64, u32, u64]
         L.orc_copy.restype = i32
         L.orc_copy.argtypes = [P(_Rec), P(_Map), C.c_void_p, P(_Map), C.c_void_p, u64, i32]
+        L.orc_linearize.restype = u64
+        L.orc_linearize.argtypes = [u32, C.c_void_p, C.c_void_p, i32]
+        L.orc_copy_nd.restype = i32
+        L.orc_copy_nd.argtypes = [P(_Rec), P(_Map), C.c_void_p, i32, P(_Map), C.c_void_p, i32, u32, C.c_void_p]
         L.orc_load_many.restype = None
         L.orc_load_many.argtypes = [P(_Rec), P(_Map), u64, C.c_void_p, C.c_void_p, C.c_void_p,
                                     u64, C.c_void_p]
@@ -190,6 +194,29 @@ def copy(rec, src_spec, src_blobs, dst_spec, n, dst_blobs=None, threads=0, fill=
     r = _rec(rec, kp)
     lib().orc_copy(C.byref(r), C.byref(_map(src_spec, kp)), _ptrs(src_blobs, kp),
                    C.byref(_map(dst_spec, kp)), _ptrs(dst_blobs, kp), n, threads)
+    return dst_blobs
+
+
+def linearize(extents, a, col_major=False):
+    """Linear index of multi-index `a` (Sec. 2 array extents), row-major unless col_major."""
+    ext = (C.c_uint64 * len(extents))(*extents)
+    idx = (C.c_uint64 * len(a))(*a)
+    return lib().orc_linearize(len(extents), ext, idx, 1 if col_major else 0)
+
+
+def copy_nd(rec, src_spec, src_blobs, dst_spec, extents, dst_blobs=None, fill=0):
+    """dst(a).f = src(a).f for every multi-index a of `extents`; a spec with
+    "col_major": True linearises its view column-major (first extent fastest)."""
+    kp = _Keep()
+    n = int(np.prod(extents, dtype=np.uint64)) if len(extents) else 0
+    if dst_blobs is None:
+        dst_blobs = alloc_blobs(rec, dst_spec, n, fill)
+    ext = (C.c_uint64 * len(extents))(*extents)
+    rc = lib().orc_copy_nd(C.byref(_rec(rec, kp)), C.byref(_map(src_spec, kp)), _ptrs(src_blobs, kp),
+                           1 if src_spec.get("col_major") else 0, C.byref(_map(dst_spec, kp)),
+                           _ptrs(dst_blobs, kp), 1 if dst_spec.get("col_major") else 0, len(extents), ext)
+    if rc != 0:
+        raise ValueError("rank must be 1..8")
     return dst_blobs
 
 

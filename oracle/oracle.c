@@ -592,6 +592,45 @@ EXPORT int orc_copy(const orc_rec* rec, const orc_map* src, uint8_t* const* sblo
   return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Array extents and their linearisation (Sec. 2 array extents).  The       */
+/* record at multi-index a = (a_0 .. a_{r-1}) of extents e sits at linear    */
+/* index  sum_k a_k * prod_{m>k} e_m  (row-major: last extent fastest) or    */
+/*        sum_k a_k * prod_{m<k} e_m  (column-major: first extent fastest).  */
+/* ------------------------------------------------------------------------ */
+
+EXPORT uint64_t orc_linearize(uint32_t rank, const uint64_t* ext, const uint64_t* a, int col_major) {
+  uint64_t lin = 0;
+  if (col_major) {
+    for (int k = (int)rank - 1; k >= 0; --k) lin = lin * ext[k] + a[k];
+  } else {
+    for (uint32_t k = 0; k < rank; ++k) lin = lin * ext[k] + a[k];
+  }
+  return lin;
+}
+
+/* dst(a).f = src(a).f for every multi-index a of the extents and every leaf
+ * f, each side linearised in its own order.  Multi-indices are visited in
+ * row-major order, one at a time. */
+EXPORT int orc_copy_nd(const orc_rec* rec, const orc_map* src, uint8_t* const* sblobs, int src_col_major,
+                       const orc_map* dst, uint8_t* const* dblobs, int dst_col_major, uint32_t rank,
+                       const uint64_t* ext) {
+  uint64_t n = 1, a[8] = {0};
+  if (rank < 1 || rank > 8) return -1;
+  for (uint32_t k = 0; k < rank; ++k) n *= ext[k];
+  for (uint64_t c = 0; c < n; ++c) {
+    const uint64_t is = orc_linearize(rank, ext, a, src_col_major);
+    const uint64_t id = orc_linearize(rank, ext, a, dst_col_major);
+    for (uint32_t f = 0; f < rec->nf; ++f) orc_store(rec, dst, n, dblobs, id, f, orc_load(rec, src, n, sblobs, is, f));
+    for (int k = (int)rank - 1; k >= 0; --k) {  /* next multi-index, last extent fastest */
+      if (++a[k] < ext[k]) break;
+      a[k] = 0;
+    }
+  }
+  clear_stream_tails(rec, dst, dblobs, n);
+  return 0;
+}
+
 /* Batched helpers for tests: values and locations of sampled elements. */
 EXPORT void orc_load_many(const orc_rec* rec, const orc_map* m, uint64_t n, uint8_t* const* blobs,
                           const uint64_t* idx, const uint32_t* fields, uint64_t count,

@@ -241,3 +241,58 @@ def test_null_source_and_destination():
             assert np.array_equal(o, np.where(m == 0xFF, 0, 0xA5).astype(np.uint8))
     src = oracle.store_planes(rec, {"kind": "aos"}, [np.arange(n, dtype=np.float32)] * 3)
     assert oracle.copy(rec, {"kind": "aos"}, src, {"kind": "null"}, n) == []
+
+
+# ---------------------------------------------------------------- array extents: linearisation
+
+def test_linearize_matches_numpy_both_orders():
+    """Sec. 2 array extents: row-major = numpy order 'C', column-major = order 'F'."""
+    rng = np.random.default_rng(7)
+    for rank in range(1, 6):
+        for _ in range(10):
+            ext = [int(x) for x in rng.integers(1, 6, rank)]
+            a = [int(rng.integers(0, e)) for e in ext]
+            assert oracle.linearize(ext, a) == np.ravel_multi_index(a, ext, order="C")
+            assert oracle.linearize(ext, a, col_major=True) == np.ravel_multi_index(a, ext, order="F")
+
+
+@pytest.mark.parametrize("ext", [(3, 5), (4, 3, 5), (2, 3, 2, 3), (7, 1, 4)])
+@pytest.mark.parametrize("dst", [{"kind": "soa_mb"}, {"kind": "aos"}, {"kind": "aosoa", "lanes": 4},
+                                 {"kind": "bytesplit", "inner": {"kind": "soa_sb"}}])
+def test_copy_nd_row_to_column_major_is_numpy_order_f(ext, dst):
+    """Each record holds its own row-major index; after a copy into a column-major
+    view, linear position j holds the row-major index of the multi-index whose
+    column-major index is j: numpy's C-to-F reordering of arange."""
+    rec = ["i32", "f32", "u32"]
+    n = int(np.prod(ext))
+    idx = np.arange(n, dtype=np.int32)
+    planes = [idx, (idx * 0.5).astype(np.float32), (idx ^ 0x5A5A).astype(np.uint32)]
+    src = oracle.store_planes(rec, {"kind": "aos"}, planes)
+    got = oracle.copy_nd(rec, {"kind": "aos"}, src, dict(dst, col_major=True), list(ext))
+    back = oracle.load_planes(rec, dst, got, n)
+    perm = np.arange(n).reshape(ext, order="C").ravel(order="F")
+    for f in range(3):
+        assert np.array_equal(back[f], planes[f][perm]), f
+    # and back to row-major restores the records
+    again = oracle.copy_nd(rec, dict(dst, col_major=True), got, {"kind": "soa_sb"}, list(ext))
+    assert all(np.array_equal(a, b) for a, b in zip(oracle.load_planes(rec, {"kind": "soa_sb"}, again, n), planes))
+
+
+def test_copy_nd_same_order_is_the_linear_copy():
+    """Two views in the same order (either one) place every record at the same
+    linear position, so the copy is the plain linear copy; so is any copy whose
+    extents have a single non-unit dimension."""
+    rec = ["f32"] * 4
+    rng = np.random.default_rng(3)
+    for ext in ([4, 6], [2, 3, 5], [1, 9, 1], [11]):
+        n = int(np.prod(ext))
+        planes = [rng.standard_normal(n).astype(np.float32) for _ in range(4)]
+        src = oracle.store_planes(rec, {"kind": "aosoa", "lanes": 8}, planes)
+        lin = oracle.copy(rec, {"kind": "aosoa", "lanes": 8}, src, {"kind": "soa_sb"}, n)
+        for so, do in ((False, False), (True, True)):
+            got = oracle.copy_nd(rec, {"kind": "aosoa", "lanes": 8, "col_major": so}, src,
+                                 {"kind": "soa_sb", "col_major": do}, ext)
+            assert all(np.array_equal(a, b) for a, b in zip(got, lin))
+        if sum(e > 1 for e in ext) <= 1:
+            got = oracle.copy_nd(rec, {"kind": "aosoa", "lanes": 8}, src, {"kind": "soa_sb", "col_major": True}, ext)
+            assert all(np.array_equal(a, b) for a, b in zip(got, lin))
