@@ -27,8 +27,9 @@
  *     Views and batches are library-owned handles that only hold pointers;
  *     the caller keeps blobs alive until work on the stream has completed.
  *   - All multi-byte values are little-endian.  Array extents are linearised
- *     row-major (last extent fastest); every operation works on the
- *     linearised record index i in [0, N), N = product of the extents.
+ *     row-major (last extent fastest) unless the view's mapping sets
+ *     LLAMA_FLAG_COL_MAJOR; every operation works on the linearised record
+ *     index i in [0, N), N = product of the extents.
  */
 #ifndef LLAMA_MI_H
 #define LLAMA_MI_H
@@ -155,6 +156,22 @@ typedef enum llama_map_kind {
 } llama_map_kind;
 
 #define LLAMA_FLAG_AOS_PACKED 0x1u /* AOS: no alignment padding between fields */
+#define LLAMA_FLAG_COL_MAJOR 0x4u  /* Sec. 2 array extents: the view linearises its
+                                      multi-index column-major, first extent fastest:
+                                      record (a_0 .. a_{r-1}) sits at linear index
+                                      sum_k a_k * prod_{m<k} e_m (row-major, the
+                                      default: sum_k a_k * prod_{m>k} e_m).  Valid on
+                                      the outermost mapping of a view only (INVALID_ARG
+                                      on an inner one).  llama_copy copies dst(a) =
+                                      src(a) for every multi-index a: views in the same
+                                      order (or whose extents have at most one entry
+                                      above 1) copy by linear index as usual; views in
+                                      different orders must have the same extents
+                                      (RECORD_MISMATCH otherwise), and the copy is a
+                                      record permutation that the GPU performs for
+                                      physical mappings with leaves of one size
+                                      (UNSUPPORTED for computed mappings and in
+                                      batches). */
 #define LLAMA_FLAG_ROUND_RNE 0x2u  /* BITPACK_FLOAT: round the mantissa to nearest,
                                       ties to even (ties compare the
                                       significand's last bit: with M = 0 the

@@ -15,6 +15,8 @@ Records are lists of leaf type names ("f32", "f64", "i8" ... "u64", "f16",
     {"kind": "null"}    {"kind": "split", "at": k, "parts": [mapping, mapping]}
     {"kind": "field_access_count", "inner": mapping}
     {"kind": "heatmap", "granularity": G, "inner": mapping}
+Any outermost mapping may add "col_major": True (extents linearised first
+extent fastest).
 """
 import ctypes as C
 import os
@@ -41,6 +43,7 @@ STATUS = {0: "OK", -1: "INVALID_ARG", -2: "UNSUPPORTED", -3: "INDEX_OVERFLOW",
           -4: "RECORD_MISMATCH", -5: "ALIGNMENT", -6: "HIP", -7: "NO_MEMORY"}
 FLAG_AOS_PACKED = 1
 FLAG_ROUND_RNE = 0x2
+FLAG_COL_MAJOR = 0x4
 
 
 class LlamaError(RuntimeError):
@@ -148,7 +151,8 @@ def _mapping(spec, keep):
     m.bits = spec.get("bits", 0)
     m.exp_bits = spec.get("exp", 0)
     m.man_bits = spec.get("man", 0)
-    m.flags = (FLAG_AOS_PACKED if spec.get("packed") else 0) | (FLAG_ROUND_RNE if spec.get("round") == "rne" else 0)
+    m.flags = ((FLAG_AOS_PACKED if spec.get("packed") else 0) | (FLAG_ROUND_RNE if spec.get("round") == "rne" else 0)
+               | (FLAG_COL_MAJOR if spec.get("col_major") else 0))
     if "stored" in spec:
         arr = (C.c_int * len(spec["stored"]))(*[SCALARS[t] for t in spec["stored"]])
         keep.append(arr)

@@ -326,6 +326,9 @@ llama_status llama_batch_create(uint32_t n, const llama_view* const* srcs, llama
   uint64_t granule = 128;
   for (uint32_t v = 0; v < n; ++v) {
     if (!srcs[v] || !dsts[v]) return fail(LLAMA_ERR_INVALID_ARG, "view is NULL");
+    if (orders_differ(srcs[v], dsts[v]))
+      return fail(LLAMA_ERR_UNSUPPORTED, "view " + std::to_string(v) +
+                                             ": batches copy views of one linearisation order only");
     Plan p;
     llama_status st = plan_copy(srcs[v], dsts[v], nullptr, p);
     if (st != LLAMA_OK) return fail(st, "view " + std::to_string(v) + ": " + llama_last_error());

@@ -89,8 +89,10 @@ llama_status copy_mapping(const Rec& rec, const llama_mapping* map, MapDesc& out
   out.exp_bits = map->exp_bits;
   out.man_bits = map->man_bits;
   out.flags = map->flags;
-  if (map->flags & ~(LLAMA_FLAG_AOS_PACKED | LLAMA_FLAG_ROUND_RNE))
+  if (map->flags & ~(LLAMA_FLAG_AOS_PACKED | LLAMA_FLAG_ROUND_RNE | LLAMA_FLAG_COL_MAJOR))
     return fail(LLAMA_ERR_INVALID_ARG, "unknown mapping flags");
+  if ((map->flags & LLAMA_FLAG_COL_MAJOR) && depth > 0)
+    return fail(LLAMA_ERR_INVALID_ARG, "LLAMA_FLAG_COL_MAJOR applies to the outermost mapping of a view");
   if ((map->flags & LLAMA_FLAG_ROUND_RNE) && map->kind != LLAMA_MAP_BITPACK_FLOAT_SOA)
     return fail(LLAMA_ERR_INVALID_ARG, "LLAMA_FLAG_ROUND_RNE applies to BITPACK_FLOAT_SOA only");
   switch (map->kind) {
@@ -679,6 +681,86 @@ llama_status plan_zero(const llama_view* dst, Plan& plan) {
   return LLAMA_OK;
 }
 
+bool orders_differ(const llama_view* a, const llama_view* b) {
+  if (a->col_major == b->col_major) return false;
+  uint32_t big = 0;  // extents above 1: with at most one, both orders coincide
+  for (uint32_t d = 0; d < a->rank; ++d) big += a->extents[d] > 1 ? 1u : 0u;
+  return big > 1;
+}
+
+llama_status plan_xpose(const llama_view* src, const llama_view* dst, Plan& plan) {
+  plan = Plan{};
+  Side& S = plan.xa.src;
+  Side& D = plan.xa.dst;
+  llama_scalar su, ss, du, ds;
+  llama_status st;
+  if ((st = make_side(src, S, su, ss)) != LLAMA_OK) return st;
+  if ((st = make_side(dst, D, du, ds)) != LLAMA_OK) return st;
+  if (S.vkind != VK_RAW || D.vkind != VK_RAW)
+    return fail(LLAMA_ERR_UNSUPPORTED,
+                "a copy between views of different linearisation orders moves physical mappings only");
+  if (S.rec_bytes != D.rec_bytes) return fail(LLAMA_ERR_RECORD_MISMATCH, "stored record sizes differ");
+  // unit extents do not change either linearisation: drop them
+  uint64_t e[8];
+  uint32_t r = 0;
+  for (uint32_t d = 0; d < src->rank; ++d)
+    if (src->extents[d] > 1) e[r++] = src->extents[d];
+  // strides of every axis in each order (records)
+  auto strides = [&](bool col, uint64_t* out) {
+    uint64_t acc = 1;
+    if (col) {
+      for (uint32_t k = 0; k < r; ++k) { out[k] = acc; acc *= e[k]; }
+    } else {
+      for (int k = (int)r - 1; k >= 0; --k) { out[k] = acc; acc *= e[k]; }
+    }
+  };
+  uint64_t ss_[8], ds_[8];
+  strides(src->col_major, ss_);
+  strides(dst->col_major, ds_);
+  const uint32_t P = dst->col_major ? 0u : r - 1u;  // the destination's fastest axis
+  const uint32_t Q = src->col_major ? 0u : r - 1u;  // the source's fastest axis
+  XposeArgs& a = plan.xa;
+  a.eP = e[P];
+  a.eQ = e[Q];
+  a.sP = ss_[P];
+  a.dQ = ds_[Q];
+  a.nmid = 0;
+  for (uint32_t k = 0; k < r; ++k) {
+    if (k == P || k == Q) continue;
+    a.mext[a.nmid] = e[k];
+    a.msrc[a.nmid] = ss_[k];
+    a.mdst[a.nmid] = ds_[k];
+    ++a.nmid;
+  }
+  const uint32_t U = std::min(S.cs, D.cs);
+  a.nunits = S.rec_bytes / U;
+  a.div_units = make_div(a.nunits);
+  // T x T records of the LDS image ([unit][q][p], rows of T + 1 units)
+  a.T = 32;
+  while (a.T > 4 && (uint64_t)S.rec_bytes * a.T * (a.T + 1) > kMaxTileLds) a.T >>= 1;
+  a.log2T = log2u(a.T);
+  a.src_rec_major = S.layout == LY_AOS ? 1u : 0u;
+  a.dst_rec_major = D.layout == LY_AOS ? 1u : 0u;
+  auto lmag = [](const Side& x) -> uint64_t {
+    if (x.layout != LY_AOSOA || (x.lanes & (x.lanes - 1)) == 0) return 0;
+    return ~0ull / x.lanes + 1ull;  // ceil(2^64 / L) for L not a power of two
+  };
+  a.src_lmag = lmag(S);
+  a.dst_lmag = lmag(D);
+  a.nPt = (a.eP + a.T - 1) / a.T;
+  a.nQt = (a.eQ + a.T - 1) / a.T;
+  uint64_t M = 1;
+  for (uint32_t k = 0; k < a.nmid; ++k) M *= a.mext[k];
+  a.ntiles = M * a.nPt * a.nQt;
+  plan.kind = PK_XPOSE;
+  plan.unit = U;
+  plan.ntiles = a.ntiles;
+  plan.grid = (uint32_t)std::min<uint64_t>(a.ntiles, 1u << 20);
+  plan.lds = (uint32_t)(((uint64_t)S.rec_bytes * a.T * (a.T + 1) + 15u) & ~15ull);
+  plan.alg_bytes = mapped_bytes(src->rec, src->map, src->n) + mapped_bytes(dst->rec, dst->map, dst->n);
+  return LLAMA_OK;
+}
+
 llama_status launch_plan(const Plan& plan, hipStream_t st) {
   if (plan.ntiles == 0) return LLAMA_OK;
   hipError_t e = hipSuccess;
@@ -688,6 +770,7 @@ llama_status launch_plan(const Plan& plan, hipStream_t st) {
     case PK_PACK: e = launch_pack(plan.args, plan.grid, plan.lds, st); break;
     case PK_ZERO: e = launch_zero(plan.args, plan.unit, plan.grid, st); break;
     case PK_UNPACK: e = launch_unpack(plan.args, plan.unit, plan.grid, plan.lds, st); break;
+    case PK_XPOSE: e = launch_xpose(plan.xa, plan.unit, plan.grid, plan.lds, st); break;
   }
   if (e != hipSuccess) return fail(LLAMA_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
   return LLAMA_OK;
@@ -744,6 +827,7 @@ llama_status llama_view_create(const llama_record* rec, const llama_mapping* map
   if ((st = read_extents(rank, extents, v->n)) != LLAMA_OK) return st;
   v->rank = rank;
   for (uint32_t d = 0; d < rank; ++d) v->extents[d] = extents[d];
+  v->col_major = (map->flags & LLAMA_FLAG_COL_MAJOR) != 0;
   if ((int)index_type < LLAMA_IDX_I16 || (int)index_type > LLAMA_IDX_U64)
     return fail(LLAMA_ERR_INVALID_ARG, "invalid index type");
   v->index_type = index_type;
@@ -810,10 +894,11 @@ static void clone_map(const MapDesc& a, MapDesc& b) {
 static bool part_view(const llama_view* v, uint32_t k, int part, llama_view& out) {
   const Rec& rec = v->rec;
   out.rec.assign(part ? rec.begin() + k : rec.begin(), part ? rec.end() : rec.begin() + k);
-  out.rank = 1;
-  out.extents[0] = v->n;
+  out.rank = v->rank;
+  for (int d = 0; d < 8; ++d) out.extents[d] = v->extents[d];
   out.n = v->n;
   out.index_type = v->index_type;
+  out.col_major = v->col_major;
   out.blobs.clear();
   out.blob_bytes.clear();
   size_t b0 = 0, b1 = 0;
@@ -853,6 +938,7 @@ static void inner_view(const llama_view* v, llama_view& out) {
   for (int d = 0; d < 8; ++d) out.extents[d] = v->extents[d];
   out.n = v->n;
   out.index_type = v->index_type;
+  out.col_major = v->col_major;
   const size_t c = blob_count(v->rec, *v->map.inner);
   out.blobs.assign(v->blobs.begin(), v->blobs.begin() + c);
   out.blob_bytes.assign(v->blob_bytes.begin(), v->blob_bytes.begin() + c);
@@ -958,6 +1044,12 @@ static llama_status plan_views(const llama_view* src, const llama_view* dst, con
   if (!src || !dst) return fail(LLAMA_ERR_INVALID_ARG, "view is NULL");
   if (src->rec != dst->rec) return fail(LLAMA_ERR_RECORD_MISMATCH, "source and destination records differ");
   if (src->n != dst->n) return fail(LLAMA_ERR_RECORD_MISMATCH, "source and destination record counts differ");
+  if (orders_differ(src, dst)) {
+    bool same = src->rank == dst->rank;
+    for (uint32_t d = 0; same && d < src->rank; ++d) same = src->extents[d] == dst->extents[d];
+    if (!same)
+      return fail(LLAMA_ERR_RECORD_MISMATCH, "views linearised in different orders need the same extents");
+  }
   if (instrumented(src) || instrumented(dst)) {
     llama_view is, id;
     if (instrumented(src)) inner_view(src, is);
@@ -985,7 +1077,10 @@ static llama_status plan_views(const llama_view* src, const llama_view* dst, con
   }
   if (dst->map.kind == LLAMA_MAP_NULL) return LLAMA_OK;
   CopyStep step;
-  llama_status s = src->map.kind == LLAMA_MAP_NULL ? plan_zero(dst, step.plan) : plan_copy(src, dst, params, step.plan);
+  llama_status s;
+  if (src->map.kind == LLAMA_MAP_NULL) s = plan_zero(dst, step.plan);  // zeros in any order
+  else if (orders_differ(src, dst)) s = plan_xpose(src, dst, step.plan);
+  else s = plan_copy(src, dst, params, step.plan);
   if (s != LLAMA_OK) return s;
   steps.push_back(step);
   return LLAMA_OK;

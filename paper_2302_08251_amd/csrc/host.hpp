@@ -46,13 +46,14 @@ struct llama_view {
   uint64_t extents[8] = {0};
   uint64_t n = 0;
   llama_index_type index_type = LLAMA_IDX_I64;
+  bool col_major = false;  // extents linearised column-major (LLAMA_FLAG_COL_MAJOR)
   std::vector<void*> blobs;
   std::vector<uint64_t> blob_bytes;  // bytes the mapping uses per blob
 };
 
 namespace lm {
 
-enum PlanKind : uint32_t { PK_RAW = 0, PK_CONV = 1, PK_PACK = 2, PK_UNPACK = 3, PK_ZERO = 4 };
+enum PlanKind : uint32_t { PK_RAW = 0, PK_CONV = 1, PK_PACK = 2, PK_UNPACK = 3, PK_ZERO = 4, PK_XPOSE = 5 };
 
 struct Plan {
   PlanKind kind = PK_RAW;
@@ -62,6 +63,7 @@ struct Plan {
   uint64_t alg_bytes = 0;  // mapped bytes read + mapped bytes written
   uint64_t ntiles = 0;
   TileArgs args{};
+  XposeArgs xa{};  // PK_XPOSE
 };
 
 // Builds the device description of a view.  UNSUPPORTED when the tile
@@ -82,6 +84,12 @@ llama_status launch_plan(const Plan& plan, hipStream_t st);
 
 // Zero fill of every mapped byte of dst (a copy from a NULL view).
 llama_status plan_zero(const llama_view* dst, Plan& plan);
+
+// True when two views place some record at different linear positions
+// because their linearisation orders differ (more than one extent above 1).
+bool orders_differ(const llama_view* a, const llama_view* b);
+// Copy between views of different linearisation orders (same extents).
+llama_status plan_xpose(const llama_view* src, const llama_view* dst, Plan& plan);
 
 // Geometry of one blob of a physical layout for Heatmap counting: records
 // come in periods of `period` bytes holding `recs` records each (AoS: one

@@ -117,4 +117,27 @@ struct TileArgs {
   Geo can;              // canonical image geometry (MERGE / SPLIT)
 };
 
+// A copy between two views linearised in different orders (row- and
+// column-major, Sec. 2 array extents): a batched 2-D transpose of records.
+// Axis P is the destination's fastest axis, axis Q the source's; the other
+// ("middle") axes are fixed per tile.  A tile holds T x T records: T
+// consecutive source records (along Q) for each of T values along P.
+// Records move in units of U bytes (U = the smaller column size of the two
+// sides).  Counts and strides are in records.
+struct XposeArgs {
+  Side src;
+  Side dst;
+  uint32_t nunits;          // units per record
+  uint32_t T, log2T;        // tile edge (a power of two)
+  uint32_t src_rec_major;   // the source keeps a record's units together (AoS)
+  uint32_t dst_rec_major;
+  uint32_t nmid;            // middle axes
+  Div div_units;
+  uint64_t src_lmag, dst_lmag;  // AoSoA: ceil(2^64 / L) (0: L is a power of two)
+  uint64_t eP, eQ;          // extents of the two tile axes
+  uint64_t sP, dQ;          // source stride of axis P, destination stride of axis Q
+  uint64_t nPt, nQt, ntiles;
+  uint64_t mext[8], msrc[8], mdst[8];  // middle axes: extent, source and destination strides
+};
+
 }  // namespace lm

@@ -11,11 +11,24 @@
 #include <mutex>
 
 #include "host.hpp"
+#include "static_view.hpp"
 #include "tile_engine.hpp"
 
 namespace lm {
 
 constexpr uint32_t NB_T = 256;  // threads per workgroup, i-particles per block, j-tile size
+
+// The j-tile cache of the update is itself a view in LDS (Sec. 2: static
+// extents make the view a trivial value type that can live in shared memory;
+// Sec. 3: Split and Null select the fields it keeps): 256 particles with
+// fully static extents and a 16-bit index type, whose Split sends
+// {pos.x, pos.y, pos.z, mass} (leaves 0, 1, 2, 6) to a 16-byte AoS record and
+// the velocities to Null.  It stores nothing but those bytes, and every offset
+// is a compile-time constant plus 16 * particle.
+using JTileExt = sv::Extents<uint16_t, NB_T>;
+using JTileMap = sv::Split<0x47ull, sv::AoS<JTileExt, 4, float>, sv::Null<JTileExt, 3, float>>;
+using JTile = sv::View<JTileMap>;
+static_assert(sizeof(JTile) == NB_T * 4 * sizeof(float), "the j-tile view holds exactly its mapped bytes");
 
 // Byte offset of column `col` of record i within its blob (physical sides).
 __device__ __forceinline__ uint32_t nb_off(const Side& s, uint32_t i, uint32_t col) {
@@ -79,7 +92,7 @@ __device__ __forceinline__ void nb_store(const Side& s, uint32_t i, uint32_t f, 
 
 __global__ __launch_bounds__(NB_T) void k_nb_update(const Side s, uint32_t n, float eps2, uint32_t per_slice,
                                                    float* __restrict__ part) {
-  __shared__ float4 tile[NB_T];
+  __shared__ JTile tile;
   const uint32_t i = blockIdx.x * NB_T + threadIdx.x;
   const uint32_t j0 = blockIdx.y * per_slice;
   uint32_t j1 = j0 + per_slice;
@@ -94,18 +107,28 @@ __global__ __launch_bounds__(NB_T) void k_nb_update(const Side s, uint32_t n, fl
   float ax = 0.f, ay = 0.f, az = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
   for (uint32_t jt = j0; jt < j1; jt += NB_T) {
     const uint32_t j = jt + threadIdx.x;
-    float4 p = {0.f, 0.f, 0.f, 0.f};  // mass 0 outside the slice: no contribution
-    if (j < j1) p = {nb_load(s, j, 0), nb_load(s, j, 1), nb_load(s, j, 2), nb_load(s, j, 6)};
-    tile[threadIdx.x] = p;
+    const uint16_t me = (uint16_t)threadIdx.x;  // this thread's particle in the j-tile
+    float px = 0.f, py = 0.f, pz = 0.f, pm = 0.f;  // mass 0 outside the slice: no contribution
+    if (j < j1) {
+      px = nb_load(s, j, 0);
+      py = nb_load(s, j, 1);
+      pz = nb_load(s, j, 2);
+      pm = nb_load(s, j, 6);
+    }
+    tile.store<0>(me, px);
+    tile.store<1>(me, py);
+    tile.store<2>(me, pz);
+    tile.store<6>(me, pm);
     __syncthreads();
     float tx = 0.f, ty = 0.f, tz = 0.f;
 #pragma unroll 8
     for (uint32_t k = 0; k < NB_T; ++k) {
-      const float4 q = tile[k];
-      const float dx = q.x - xi, dy = q.y - yi, dz = q.z - zi;
+      const uint16_t kk = (uint16_t)k;
+      const float qx = tile.load<0>(kk), qy = tile.load<1>(kk), qz = tile.load<2>(kk), qm = tile.load<6>(kk);
+      const float dx = qx - xi, dy = qy - yi, dz = qz - zi;
       const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2)));
       const float inv = __builtin_amdgcn_rsqf(r2);
-      const float w = q.w * inv * inv * inv;
+      const float w = qm * inv * inv * inv;
       tx = __builtin_fmaf(dx, w, tx);
       ty = __builtin_fmaf(dy, w, ty);
       tz = __builtin_fmaf(dz, w, tz);

@@ -153,3 +153,16 @@ def test_copy_errors_before_gpu_work():
     assert err(lm.llama_copy, het, het2) == "UNSUPPORTED"
     for v in (a, b, c, d, e, big, het, het2):
         lm.llama_view_destroy(v)
+
+
+def test_column_major_flag_outermost_only():
+    import ctypes as C
+    rec = ["f32"] * 3
+    n = lm.llama_mapping_blob_count(rec, {"kind": "aos", "col_major": True})
+    assert n == 1
+    with pytest.raises(lm.LlamaError) as e:
+        lm.llama_mapping_blob_count(rec, {"kind": "bytesplit", "inner": {"kind": "aos", "col_major": True}})
+    assert e.value.name == "INVALID_ARG"
+    # the order does not change blob sizes
+    assert lm.llama_mapping_blob_size(rec, {"kind": "aosoa", "lanes": 8, "col_major": True}, [3, 5], 0) == \
+        lm.llama_mapping_blob_size(rec, {"kind": "aosoa", "lanes": 8}, [3, 5], 0)
