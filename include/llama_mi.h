@@ -310,7 +310,14 @@ llama_status llama_batch_destroy(llama_batch* batch);
  *   a_i = sum_j m_j (x_j - x_i) (|x_j - x_i|^2 + eps2)^(-3/2)   (G = 1)
  *   v_i <- v_i + dt a_i  (all i, from the positions before the step)
  *   x_i <- x_i + dt v_i  (with v_i as stored through the mapping)
- * Scratch memory is allocated by the library on first use per device. */
+ * Scratch memory is allocated by the library on first use per device.
+ * Instrumented views (Sec. 4): a FIELD_ACCESS_COUNT view over any of the
+ * storage forms above, or a HEATMAP view over physical F32 storage, counts
+ * every access the step makes through it: per step, each particle's
+ * position leaves are loaded once by the update and once per block of 256
+ * i-particles as a j-tile entry (with its mass), and the move loads and
+ * stores each position and velocity leaf once.  Counts add to the counter
+ * blobs as for llama_copy. */
 llama_status nbody_step(llama_view* particles, uint32_t steps, float dt, float eps2,
                         void* stream);
 
@@ -332,7 +339,8 @@ llama_status nbody_step_noalloc(llama_view* particles, uint32_t steps, float dt,
 /* Total energy  E = 1/2 sum_i m_i |v_i|^2 - sum_{i<j} m_i m_j (|x_i-x_j|^2+eps2)^(-1/2)
  * computed on the GPU in FP64 with a fixed reduction order (deterministic),
  * from the values as decoded through the mapping.  Blocks until the result
- * is on the host. */
+ * is on the host.  An instrumented view counts one load of every leaf of
+ * every particle. */
 llama_status nbody_energy(const llama_view* particles, float eps2, double* energy,
                           void* stream);
 

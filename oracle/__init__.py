@@ -70,6 +70,10 @@ def lib():
         L.orc_linearize.argtypes = [u32, C.c_void_p, C.c_void_p, i32]
         L.orc_copy_nd.restype = i32
         L.orc_copy_nd.argtypes = [P(_Rec), P(_Map), C.c_void_p, i32, P(_Map), C.c_void_p, i32, u32, C.c_void_p]
+        L.orc_nbody_view.restype = None
+        L.orc_nbody_view.argtypes = [P(_Rec), P(_Map), C.c_void_p, u64, u32, C.c_double, C.c_double, u32]
+        L.orc_energy_view.restype = C.c_double
+        L.orc_energy_view.argtypes = [P(_Rec), P(_Map), C.c_void_p, u64, C.c_double]
         L.orc_load_many.restype = None
         L.orc_load_many.argtypes = [P(_Rec), P(_Map), u64, C.c_void_p, C.c_void_p, C.c_void_p,
                                     u64, C.c_void_p]
@@ -305,6 +309,22 @@ def energy(pos, vel, mass, eps2, threads=0):
     mass = np.ascontiguousarray(mass, dtype=np.float64)
     return lib().orc_energy(pos.ctypes.data, vel.ctypes.data, mass.ctypes.data, len(mass), eps2,
                             threads)
+
+
+def nbody_view(rec, spec, blobs, n, steps, dt, eps2, tile=256):
+    """FP64 n-body reading and writing the particles through `spec` (blobs updated in
+    place), one access at a time in a tiled update's access pattern, so that
+    instrumented mappings count every access (Sec. 4, Sec. 5)."""
+    kp = _Keep()
+    lib().orc_nbody_view(C.byref(_rec(rec, kp)), C.byref(_map(spec, kp)), _ptrs(blobs, kp), n, steps, dt, eps2,
+                         tile)
+    return blobs
+
+
+def energy_view(rec, spec, blobs, n, eps2):
+    """Energy of the particles as loaded through `spec`, every leaf loaded once."""
+    kp = _Keep()
+    return lib().orc_energy_view(C.byref(_rec(rec, kp)), C.byref(_map(spec, kp)), _ptrs(blobs, kp), n, eps2)
 
 
 def max_threads():

@@ -754,6 +754,93 @@ EXPORT double orc_energy(const double* pos, const double* vel, const double* mas
   return kin - pot;
 }
 
+/* ------------------------------------------------------------------------ */
+/* The n-body consumer through a mapping (Sec. 5, instrumented as in Sec. 4) */
+/* Same steps as orc_nbody, in FP64, but every value is loaded from and      */
+/* stored to the particle view's blobs through the mapping, one access at a  */
+/* time, in the access pattern of an update that stages j-particles in tiles: */
+/*   per step: each particle's position once; for each block of `tile`      */
+/*   i-particles, every j-particle's position and mass once; then for every  */
+/*   particle and component c: load v_c, store v_c + dt a_c, load x_c, store */
+/*   x_c + dt v_c.  An instrumented mapping counts them all.                 */
+/* Leaves: pos.x pos.y pos.z vel.x vel.y vel.z mass, all F32 or all F64.     */
+/* ------------------------------------------------------------------------ */
+
+static double as_double(uint64_t bits, int t) {
+  if (t == ORC_F64) { double d; memcpy(&d, &bits, 8); return d; }
+  uint32_t u = (uint32_t)bits;
+  float f;
+  memcpy(&f, &u, 4);
+  return (double)f;
+}
+
+static uint64_t from_double(double d, int t) {
+  if (t == ORC_F64) { uint64_t b; memcpy(&b, &d, 8); return b; }
+  float f = (float)d;
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  return u;
+}
+
+EXPORT void orc_nbody_view(const orc_rec* rec, const orc_map* m, uint8_t* const* blobs, uint64_t n,
+                           uint32_t steps, double dt, double eps2, uint32_t tile) {
+  const int t = rec->types[0];
+  double* xi = (double*)malloc(sizeof(double) * 3 * (n ? n : 1));
+  double* acc = (double*)malloc(sizeof(double) * 3 * (n ? n : 1));
+  for (uint32_t step = 0; step < steps; ++step) {
+    for (uint64_t i = 0; i < n; ++i)
+      for (uint32_t c = 0; c < 3; ++c) xi[3 * i + c] = as_double(orc_load(rec, m, n, blobs, i, c), t);
+    for (uint64_t i = 0; i < 3 * n; ++i) acc[i] = 0;
+    for (uint64_t b = 0; b < n; b += tile) {
+      const uint64_t e = b + tile < n ? b + tile : n;
+      for (uint64_t j = 0; j < n; ++j) {
+        double xj[3], mj;
+        for (uint32_t c = 0; c < 3; ++c) xj[c] = as_double(orc_load(rec, m, n, blobs, j, c), t);
+        mj = as_double(orc_load(rec, m, n, blobs, j, 6), t);
+        for (uint64_t i = b; i < e; ++i) {
+          double d[3], r2 = eps2;
+          for (uint32_t c = 0; c < 3; ++c) {
+            d[c] = xj[c] - xi[3 * i + c];
+            r2 += d[c] * d[c];
+          }
+          const double w = mj / (r2 * sqrt(r2));
+          for (uint32_t c = 0; c < 3; ++c) acc[3 * i + c] += d[c] * w;
+        }
+      }
+    }
+    for (uint64_t i = 0; i < n; ++i)
+      for (uint32_t c = 0; c < 3; ++c) {
+        const double v = as_double(orc_load(rec, m, n, blobs, i, 3 + c), t) + dt * acc[3 * i + c];
+        orc_store(rec, m, n, blobs, i, 3 + c, from_double(v, t));
+        const double x = as_double(orc_load(rec, m, n, blobs, i, c), t) + dt * v;
+        orc_store(rec, m, n, blobs, i, c, from_double(x, t));
+      }
+  }
+  free(xi);
+  free(acc);
+}
+
+/* Energy through the mapping: every leaf of every particle loaded once. */
+EXPORT double orc_energy_view(const orc_rec* rec, const orc_map* m, uint8_t* const* blobs, uint64_t n,
+                              double eps2) {
+  const int t = rec->types[0];
+  double* p = (double*)malloc(sizeof(double) * 7 * (n ? n : 1));
+  for (uint64_t i = 0; i < n; ++i)
+    for (uint32_t f = 0; f < 7; ++f) p[7 * i + f] = as_double(orc_load(rec, m, n, blobs, i, f), t);
+  double kin = 0, pot = 0;
+  for (uint64_t i = 0; i < n; ++i) {
+    const double* a = p + 7 * i;
+    kin += 0.5 * a[6] * (a[3] * a[3] + a[4] * a[4] + a[5] * a[5]);
+    for (uint64_t j = i + 1; j < n; ++j) {
+      const double* b = p + 7 * j;
+      const double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+      pot += a[6] * b[6] / sqrt(dx * dx + dy * dy + dz * dz + eps2);
+    }
+  }
+  free(p);
+  return kin - pot;
+}
+
 EXPORT int orc_max_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

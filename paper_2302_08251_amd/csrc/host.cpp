@@ -776,6 +776,45 @@ llama_status launch_plan(const Plan& plan, hipStream_t st) {
   return LLAMA_OK;
 }
 
+static void clone_map(const MapDesc& a, MapDesc& b) {
+  b.kind = a.kind;
+  b.lanes = a.lanes;
+  b.bits = a.bits;
+  b.exp_bits = a.exp_bits;
+  b.man_bits = a.man_bits;
+  b.flags = a.flags;
+  b.stored = a.stored;
+  b.inner.reset();
+  b.inner2.reset();
+  if (a.inner) {
+    b.inner.reset(new MapDesc);
+    clone_map(*a.inner, *b.inner);
+  }
+  if (a.inner2) {
+    b.inner2.reset(new MapDesc);
+    clone_map(*a.inner2, *b.inner2);
+  }
+}
+
+bool instrumented(const llama_view* v) {
+  return v->map.kind == LLAMA_MAP_FIELD_ACCESS_COUNT || v->map.kind == LLAMA_MAP_HEATMAP;
+}
+
+// The view an instrumentation mapping forwards to: its inner mapping over the
+// leading blobs.
+void inner_view(const llama_view* v, llama_view& out) {
+  out.rec = v->rec;
+  clone_map(*v->map.inner, out.map);
+  out.rank = v->rank;
+  for (int d = 0; d < 8; ++d) out.extents[d] = v->extents[d];
+  out.n = v->n;
+  out.index_type = v->index_type;
+  out.col_major = v->col_major;
+  const size_t c = blob_count(v->rec, *v->map.inner);
+  out.blobs.assign(v->blobs.begin(), v->blobs.begin() + c);
+  out.blob_bytes.assign(v->blob_bytes.begin(), v->blob_bytes.begin() + c);
+}
+
 }  // namespace lm
 
 using namespace lm;
@@ -869,25 +908,6 @@ llama_status llama_view_records(const llama_view* view, uint64_t* n) {
   return LLAMA_OK;
 }
 
-static void clone_map(const MapDesc& a, MapDesc& b) {
-  b.kind = a.kind;
-  b.lanes = a.lanes;
-  b.bits = a.bits;
-  b.exp_bits = a.exp_bits;
-  b.man_bits = a.man_bits;
-  b.flags = a.flags;
-  b.stored = a.stored;
-  b.inner.reset();
-  b.inner2.reset();
-  if (a.inner) {
-    b.inner.reset(new MapDesc);
-    clone_map(*a.inner, *b.inner);
-  }
-  if (a.inner2) {
-    b.inner2.reset(new MapDesc);
-    clone_map(*a.inner2, *b.inner2);
-  }
-}
 
 // Part `part` (fields [0, k) or [k, F)) of a view that can be divided by
 // fields: a SPLIT at k, SOA_MB (one blob per field) or NULL.
@@ -925,24 +945,6 @@ static bool part_view(const llama_view* v, uint32_t k, int part, llama_view& out
   return true;
 }
 
-static bool instrumented(const llama_view* v) {
-  return v->map.kind == LLAMA_MAP_FIELD_ACCESS_COUNT || v->map.kind == LLAMA_MAP_HEATMAP;
-}
-
-// The view an instrumentation mapping forwards to: its inner mapping over the
-// leading blobs.
-static void inner_view(const llama_view* v, llama_view& out) {
-  out.rec = v->rec;
-  clone_map(*v->map.inner, out.map);
-  out.rank = v->rank;
-  for (int d = 0; d < 8; ++d) out.extents[d] = v->extents[d];
-  out.n = v->n;
-  out.index_type = v->index_type;
-  out.col_major = v->col_major;
-  const size_t c = blob_count(v->rec, *v->map.inner);
-  out.blobs.assign(v->blobs.begin(), v->blobs.begin() + c);
-  out.blob_bytes.assign(v->blob_bytes.begin(), v->blob_bytes.begin() + c);
-}
 
 static uint32_t log2u(uint64_t x) {
   uint32_t l = 0;

@@ -85,6 +85,11 @@ llama_status launch_plan(const Plan& plan, hipStream_t st);
 // Zero fill of every mapped byte of dst (a copy from a NULL view).
 llama_status plan_zero(const llama_view* dst, Plan& plan);
 
+// FIELD_ACCESS_COUNT or HEATMAP view, and the view its inner mapping forms
+// over the leading (data) blobs.
+bool instrumented(const llama_view* v);
+void inner_view(const llama_view* v, llama_view& out);
+
 // True when two views place some record at different linear positions
 // because their linearisation orders differ (more than one extent above 1).
 bool orders_differ(const llama_view* a, const llama_view* b);

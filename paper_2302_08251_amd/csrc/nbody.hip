@@ -87,11 +87,69 @@ __device__ __forceinline__ void nb_store(const Side& s, uint32_t i, uint32_t f, 
 }
 
 // ---------------------------------------------------------------------------
+// Instrumentation of the consumer (Sec. 4): every load and store the kernels
+// make through an instrumented particle view adds one to its counters.
+// FieldAccessCount: counter 2f counts the loads of leaf f, 2f + 1 its
+// stores.  Heatmap: one counter per G bytes of each data blob; an access adds
+// one to every counter whose bytes it touches.  Counts are aggregated per
+// wave (and per workgroup where the same counter repeats) before the global
+// atomic add, so they are the per-access counts with far fewer atomics.
+// ---------------------------------------------------------------------------
+
+struct NbCount {
+  uint64_t* fac;        // FieldAccessCount counters (14), or null
+  uint64_t* heat[7];    // Heatmap: counter blob of the data blob holding leaf f, or null
+  uint32_t heat_shift;  // log2 of the bytes per Heatmap counter
+  uint32_t pad;
+};
+
+__device__ __forceinline__ uint64_t wave_ballot(bool b) { return __builtin_amdgcn_ballot_w64(b); }
+
+// FieldAccessCount: adds the wave's sum of `v` (one lane's accesses) to
+// counter k (lane 0 of the wave adds).
+__device__ __forceinline__ void nb_fac_add(const NbCount& c, uint32_t k, uint32_t v) {
+  if (!c.fac) return;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (lane_id() == 0 && v) atomicAdd((unsigned long long*)(c.fac + k), (unsigned long long)v);
+}
+
+// Heatmap: one access of the 4-byte element of leaf f at byte `off` of its
+// blob, by the lanes with `valid`; lanes that hit the same counter add once.
+__device__ __forceinline__ void nb_heat(const NbCount& c, uint32_t f, uint32_t off, bool valid) {
+  uint64_t* ctr = c.heat[f];
+  if (!ctr) return;
+  const uint32_t sh = c.heat_shift;
+  const uint32_t first = off >> sh, last = (off + 3u) >> sh;
+  for (uint32_t k = 0; k <= (3u >> (sh < 2u ? sh : 2u)); ++k) {  // counters an element can touch
+    const uint32_t q = first + k;
+    bool act = valid && q <= last;
+    uint64_t pending = wave_ballot(act);
+    while (pending) {
+      const uint32_t leader = (uint32_t)__builtin_ctzll(pending);
+      const uint32_t lq = (uint32_t)__builtin_amdgcn_readlane((int)q, (int)leader);
+      const uint64_t same = wave_ballot(act && q == lq);
+      if (lane_id() == leader) atomicAdd((unsigned long long*)(ctr + lq), (unsigned long long)__builtin_popcountll(same));
+      act = act && q != lq;
+      pending &= ~same;
+    }
+  }
+}
+
+// one access (load: which = 0, store: 1) of leaf f of particle i by the
+// lanes with `valid`
+__device__ __forceinline__ void nb_count(const NbCount& c, const Side& s, uint32_t f, uint32_t which, uint32_t i,
+                                         bool valid) {
+  nb_fac_add(c, 2u * f + which, valid ? 1u : 0u);
+  if (c.heat[f]) nb_heat(c, f, valid ? nb_off(s, i, f) : 0u, valid);
+}
+
+// ---------------------------------------------------------------------------
 // Update: partial accelerations of i-block blockIdx.x over j-slice blockIdx.y
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(NB_T) void k_nb_update(const Side s, uint32_t n, float eps2, uint32_t per_slice,
-                                                   float* __restrict__ part) {
+                                                   float* __restrict__ part, const NbCount cnt) {
   __shared__ JTile tile;
   const uint32_t i = blockIdx.x * NB_T + threadIdx.x;
   const uint32_t j0 = blockIdx.y * per_slice;
@@ -103,6 +161,11 @@ __global__ __launch_bounds__(NB_T) void k_nb_update(const Side s, uint32_t n, fl
     yi = nb_load(s, i, 1);
     zi = nb_load(s, i, 2);
   }
+  // counted once per particle: in the first slice of each i-block
+  const bool counting = cnt.fac || cnt.heat[0];
+  if (counting && blockIdx.y == 0)
+    for (uint32_t f = 0; f < 3; ++f) nb_count(cnt, s, f, 0, i, i < n);
+  uint32_t jloads = 0;  // j-tile loads of this thread (each of leaves 0, 1, 2, 6)
   // running sums with compensation (Kahan) across j-tiles
   float ax = 0.f, ay = 0.f, az = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
   for (uint32_t jt = j0; jt < j1; jt += NB_T) {
@@ -114,6 +177,13 @@ __global__ __launch_bounds__(NB_T) void k_nb_update(const Side s, uint32_t n, fl
       py = nb_load(s, j, 1);
       pz = nb_load(s, j, 2);
       pm = nb_load(s, j, 6);
+      ++jloads;
+    }
+    if (counting && cnt.heat[0]) {
+      nb_heat(cnt, 0, j < j1 ? nb_off(s, j, 0) : 0u, j < j1);
+      nb_heat(cnt, 1, j < j1 ? nb_off(s, j, 1) : 0u, j < j1);
+      nb_heat(cnt, 2, j < j1 ? nb_off(s, j, 2) : 0u, j < j1);
+      nb_heat(cnt, 6, j < j1 ? nb_off(s, j, 6) : 0u, j < j1);
     }
     tile.store<0>(me, px);
     tile.store<1>(me, py);
@@ -145,6 +215,12 @@ __global__ __launch_bounds__(NB_T) void k_nb_update(const Side s, uint32_t n, fl
     p[n + i] = ay;
     p[2u * n + i] = az;
   }
+  if (cnt.fac) {
+    nb_fac_add(cnt, 0, jloads);
+    nb_fac_add(cnt, 2, jloads);
+    nb_fac_add(cnt, 4, jloads);
+    nb_fac_add(cnt, 12, jloads);
+  }
 }
 
 __device__ __forceinline__ void nb_accel(const float* __restrict__ part, uint32_t n, uint32_t slices, uint32_t i,
@@ -160,8 +236,16 @@ __device__ __forceinline__ void nb_accel(const float* __restrict__ part, uint32_
 
 // Kick (v += dt a) then drift (x += dt v as stored), physical storage.
 __global__ __launch_bounds__(NB_T) void k_nb_kick_drift(const Side s, uint32_t n, float dt, uint32_t slices,
-                                                       const float* __restrict__ part) {
+                                                       const float* __restrict__ part, const NbCount cnt) {
   const uint32_t i = blockIdx.x * NB_T + threadIdx.x;
+  if (cnt.fac || cnt.heat[0]) {  // vel loaded and stored, then pos loaded and stored
+    for (uint32_t c = 0; c < 3; ++c) {
+      nb_count(cnt, s, 3 + c, 0, i, i < n);
+      nb_count(cnt, s, 3 + c, 1, i, i < n);
+      nb_count(cnt, s, c, 0, i, i < n);
+      nb_count(cnt, s, c, 1, i, i < n);
+    }
+  }
   if (i >= n) return;
   float a[3];
   nb_accel(part, n, slices, i, a[0], a[1], a[2]);
@@ -178,10 +262,16 @@ __global__ __launch_bounds__(NB_T) void k_nb_kick_drift(const Side s, uint32_t n
 // staged in LDS and the stream words (a tile is a whole number of words)
 // are assembled and stored by one lane each.
 __global__ __launch_bounds__(NB_T) void k_nb_kick_drift_stream(const Side s, uint32_t n, float dt,
-                                                              uint32_t slices, const float* __restrict__ part) {
+                                                              uint32_t slices, const float* __restrict__ part,
+                                                              const NbCount cnt) {
   __shared__ uint32_t codes[6][NB_T];
   const uint32_t i0 = blockIdx.x * NB_T;
   const uint32_t i = i0 + threadIdx.x;
+  if (cnt.fac)
+    for (uint32_t f = 0; f < 6; ++f) {  // every position and velocity code loaded once and stored once
+      nb_fac_add(cnt, 2u * f, i < n ? 1u : 0u);
+      nb_fac_add(cnt, 2u * f + 1u, i < n ? 1u : 0u);
+    }
   const uint32_t nt = n - i0 < NB_T ? n - i0 : NB_T;
   const uint32_t E = s.exp_bits, M = s.man_bits, B = s.bits;
   if (i < n) {
@@ -217,8 +307,11 @@ __global__ __launch_bounds__(NB_T) void k_nb_kick_drift_stream(const Side s, uin
 // Energy in FP64 (deterministic fixed-order reductions)
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(NB_T) void k_nb_decode64(const Side s, uint32_t n, double* __restrict__ d) {
+__global__ __launch_bounds__(NB_T) void k_nb_decode64(const Side s, uint32_t n, double* __restrict__ d,
+                                                     const NbCount cnt) {
   const uint32_t i = blockIdx.x * NB_T + threadIdx.x;
+  if (cnt.fac || cnt.heat[0])
+    for (uint32_t f = 0; f < 7; ++f) nb_count(cnt, s, f, 0, i, i < n);
   if (i >= n) return;
   for (uint32_t f = 0; f < 7; ++f) d[(size_t)f * n + i] = (double)nb_load(s, i, f);
 }
@@ -355,12 +448,31 @@ llama_status scratch_get(size_t bytes, hipStream_t st, void** out, double** host
   return LLAMA_OK;
 }
 
-llama_status nb_side(const llama_view* v, Side& s) {
-  if (!v) return fail(LLAMA_ERR_INVALID_ARG, "view is NULL");
-  if (v->rec.size() != 7) return fail(LLAMA_ERR_INVALID_ARG, "n-body needs the 7-field particle record");
-  for (auto t : v->rec)
-    if (t != v->rec[0] || (t != LLAMA_F32 && t != LLAMA_F64))
+// The data side of a particle view and, for FIELD_ACCESS_COUNT and HEATMAP
+// views, the counters every access adds to (Sec. 4).
+llama_status nb_side(const llama_view* vin, Side& s, NbCount& cnt) {
+  if (!vin) return fail(LLAMA_ERR_INVALID_ARG, "view is NULL");
+  if (vin->rec.size() != 7) return fail(LLAMA_ERR_INVALID_ARG, "n-body needs the 7-field particle record");
+  for (auto t : vin->rec)
+    if (t != vin->rec[0] || (t != LLAMA_F32 && t != LLAMA_F64))
       return fail(LLAMA_ERR_INVALID_ARG, "n-body needs 7 F32 or 7 F64 leaves");
+  cnt = NbCount{};
+  llama_view inner;
+  const llama_view* v = vin;
+  if (instrumented(vin)) {
+    inner_view(vin, inner);
+    v = &inner;
+    const size_t c = inner.blobs.size();  // the counter blobs follow the data blobs
+    if (vin->map.kind == LLAMA_MAP_FIELD_ACCESS_COUNT) {
+      cnt.fac = (uint64_t*)vin->blobs[c];
+    } else {
+      uint32_t sh = 0;
+      while ((1u << sh) < vin->map.lanes) ++sh;
+      cnt.heat_shift = sh;
+      const bool per_field = inner.map.kind == LLAMA_MAP_SOA_MB;
+      for (uint32_t f = 0; f < 7; ++f) cnt.heat[f] = (uint64_t*)vin->blobs[c + (per_field ? f : 0u)];
+    }
+  }
   llama_scalar ut, st;
   llama_status r = make_side(v, s, ut, st);
   if (r != LLAMA_OK) return r;
@@ -392,19 +504,19 @@ constexpr uint32_t kNoallocMaxParticles = (uint32_t)(kStaticScratchBytes / 12u);
 
 // The launches of `steps` update + move steps, partial sums in `part`
 // (nb_scratch_bytes(n) bytes; every element read is written first).
-llama_status nb_launch_steps(const Side& s, uint32_t n, uint32_t steps, float dt, float eps2, float* part,
-                             hipStream_t st) {
+llama_status nb_launch_steps(const Side& s, const NbCount& cnt, uint32_t n, uint32_t steps, float dt, float eps2,
+                             float* part, hipStream_t st) {
   const uint32_t slices = nb_slices(n);
   uint32_t per = (n + slices - 1) / slices;
   per = (per + NB_T - 1) / NB_T * NB_T;
   const uint32_t iblocks = (n + NB_T - 1) / NB_T;
   const uint32_t used = (n + per - 1) / per;
   for (uint32_t k = 0; k < steps; ++k) {
-    hipLaunchKernelGGL(k_nb_update, dim3(iblocks, used), dim3(NB_T), 0, st, s, n, eps2, per, part);
+    hipLaunchKernelGGL(k_nb_update, dim3(iblocks, used), dim3(NB_T), 0, st, s, n, eps2, per, part, cnt);
     if (s.layout == LY_STREAM)
-      hipLaunchKernelGGL(k_nb_kick_drift_stream, dim3(iblocks), dim3(NB_T), 0, st, s, n, dt, used, part);
+      hipLaunchKernelGGL(k_nb_kick_drift_stream, dim3(iblocks), dim3(NB_T), 0, st, s, n, dt, used, part, cnt);
     else
-      hipLaunchKernelGGL(k_nb_kick_drift, dim3(iblocks), dim3(NB_T), 0, st, s, n, dt, used, part);
+      hipLaunchKernelGGL(k_nb_kick_drift, dim3(iblocks), dim3(NB_T), 0, st, s, n, dt, used, part, cnt);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(LLAMA_ERR_HIP, std::string("n-body launch: ") + hipGetErrorString(e));
@@ -421,7 +533,8 @@ extern "C" {
 llama_status nbody_step(llama_view* view, uint32_t steps, float dt, float eps2, void* stream) {
   clear_error();
   Side s;
-  llama_status r = nb_side(view, s);
+  NbCount cnt;
+  llama_status r = nb_side(view, s, cnt);
   if (r != LLAMA_OK) return r;
   if (!(eps2 > 0.f)) return fail(LLAMA_ERR_INVALID_ARG, "eps2 must be > 0");
   const uint32_t n = (uint32_t)view->n;
@@ -429,13 +542,14 @@ llama_status nbody_step(llama_view* view, uint32_t steps, float dt, float eps2, 
   hipStream_t st = (hipStream_t)stream;
   void* buf;
   if ((r = scratch_get(nb_scratch_bytes(n), st, &buf, nullptr)) != LLAMA_OK) return r;
-  return nb_launch_steps(s, n, steps, dt, eps2, (float*)buf, st);
+  return nb_launch_steps(s, cnt, n, steps, dt, eps2, (float*)buf, st);
 }
 
 llama_status nbody_step_noalloc(llama_view* view, uint32_t steps, float dt, float eps2, void* stream) {
   clear_error();
   Side s;
-  llama_status r = nb_side(view, s);
+  NbCount cnt;
+  llama_status r = nb_side(view, s, cnt);
   if (r != LLAMA_OK) return r;
   if (!(eps2 > 0.f)) return fail(LLAMA_ERR_INVALID_ARG, "eps2 must be > 0");
   const uint32_t n = (uint32_t)view->n;
@@ -448,14 +562,15 @@ llama_status nbody_step_noalloc(llama_view* view, uint32_t steps, float dt, floa
   if (n == 0 || steps == 0) return LLAMA_OK;
   void* buf;
   if ((r = static_scratch_get(&buf)) != LLAMA_OK) return r;
-  return nb_launch_steps(s, n, steps, dt, eps2, (float*)buf, (hipStream_t)stream);
+  return nb_launch_steps(s, cnt, n, steps, dt, eps2, (float*)buf, (hipStream_t)stream);
 }
 
 llama_status nbody_energy(const llama_view* view, float eps2, double* energy, void* stream) {
   clear_error();
   if (!energy) return fail(LLAMA_ERR_INVALID_ARG, "energy is NULL");
   Side s;
-  llama_status r = nb_side(view, s);
+  NbCount cnt;
+  llama_status r = nb_side(view, s, cnt);
   if (r != LLAMA_OK) return r;
   const uint32_t n = (uint32_t)view->n;
   hipStream_t st = (hipStream_t)stream;
@@ -474,7 +589,7 @@ llama_status nbody_energy(const llama_view* view, float eps2, double* energy, vo
   double* pot = d + (size_t)7 * n;
   double* kin = pot + (size_t)nb * nb;
   double* out = kin + nb;
-  hipLaunchKernelGGL(k_nb_decode64, dim3(nb), dim3(NB_T), 0, st, s, n, d);
+  hipLaunchKernelGGL(k_nb_decode64, dim3(nb), dim3(NB_T), 0, st, s, n, d, cnt);
   hipLaunchKernelGGL(k_nb_potential, dim3(nb, nb), dim3(NB_T), 0, st, (const double*)d, n, (double)eps2, pot);
   hipLaunchKernelGGL(k_nb_kinetic, dim3(nb), dim3(NB_T), 0, st, (const double*)d, n, kin);
   hipLaunchKernelGGL(k_nb_final, dim3(1), dim3(NB_T), 0, st, (const double*)kin, nb, (const double*)pot, nb * nb, out);

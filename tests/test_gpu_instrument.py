@@ -8,6 +8,7 @@ import oracle
 from gpu_helpers import F32x7, assert_blobs_equal, bits_planes, download, say, upload
 
 import paper_2302_08251_amd as lm
+from paper_2302_08251_amd import synth
 
 pytestmark = pytest.mark.gpu
 
@@ -132,9 +133,6 @@ def test_rejected_uses():
     with pytest.raises(lm.LlamaError) as e:
         lm.Batch([sv], [dv])
     assert e.value.name == "UNSUPPORTED"
-    with pytest.raises(lm.LlamaError) as e:
-        lm.nbody_step(sv, 1, 0.01, 0.01)
-    assert e.value.name == "UNSUPPORTED"
 
 
 def test_heatmap_soa_blob_beyond_4_gib():
@@ -198,3 +196,31 @@ def test_instrumented_parts_and_null(n):
     lm.llama_copy(lm.View(F32x7, null, [n]), v3)
     oracle.copy(F32x7, null, [], hd, n, dst_blobs=d3)
     assert_blobs_equal(download(v3), d3, "stores from null")
+
+
+@pytest.mark.parametrize("n", [3001, 256])
+@pytest.mark.parametrize("spec", [fac({"kind": "soa_mb"}), fac({"kind": "bitpack_float", "exp": 8, "man": 15}),
+                                  heat({"kind": "soa_mb"}, 128), heat({"kind": "aos"}, 4),
+                                  heat({"kind": "aosoa", "lanes": 32}, 1)],
+                         ids=["fac_soa_mb", "fac_e8m15", "heat128_soa_mb", "heat4_aos", "heat1_aosoa32"])
+def test_instrumented_nbody_counts_every_access(spec, n):
+    """The n-body consumer through an instrumented view (Sec. 4): every load and
+    store its kernels make adds to the counters; bit-exact against the oracle's
+    n-body through the same mapping with the same access pattern (a particle's
+    position once per update, every j-particle's position and mass once per
+    256-particle i-block, the move's loads and stores), over two steps and one
+    energy check."""
+    rec = F32x7
+    inner = spec["inner"]
+    planes = [p.astype(np.float32) for p in synth.particles(n, 4)]
+    host = host_blobs(rec, spec, n, planes)
+    say("instrumented nbody", spec, n)
+    v = view(rec, spec, n, host)
+    lm.nbody_step(v, 2, 1e-4, 0.01)
+    lm.nbody_energy(v, 0.01)
+    got = download(v)
+    oracle.nbody_view(rec, spec, host, n, 2, 1e-4, 0.01, tile=256)
+    oracle.energy_view(rec, spec, host, n, 0.01)
+    nin = oracle.blob_count(rec, inner)
+    assert_blobs_equal(got[nin:], host[nin:], "counters")
+    v.close()

@@ -9,6 +9,7 @@ N = 8 high-precision (50-digit Decimal) evaluation, and the two-body energy.
 from decimal import Decimal, getcontext
 
 import numpy as np
+import pytest
 
 import oracle
 
@@ -93,3 +94,63 @@ def test_energy_drift_small_for_small_steps():
     p, v = oracle.nbody(pos, vel, mass, 20, 1e-5, 0.01)
     e1 = oracle.energy(p, v, mass, 0.01)
     assert abs(e1 - e0) / abs(e0) < 1e-5
+
+
+# ---------------------------------------------------------------- n-body through a mapping (Sec. 4, Sec. 5)
+
+def _state(n, seed, dtype):
+    from paper_2302_08251_amd import synth
+    return synth.particles(n, seed, dtype=dtype)
+
+
+def test_nbody_view_equals_the_plain_fp64_oracle():
+    n, steps = 300, 3
+    planes = _state(n, 5, np.float64)
+    rec = ["f64"] * 7
+    spec = {"kind": "aosoa", "lanes": 8}
+    blobs = oracle.store_planes(rec, spec, planes)
+    oracle.nbody_view(rec, spec, blobs, n, steps, 1e-4, 0.01, tile=64)
+    got = oracle.load_planes(rec, spec, blobs, n)
+    rp, rv = oracle.nbody(np.stack(planes[0:3], 1), np.stack(planes[3:6], 1), planes[6], steps, 1e-4, 0.01)
+    assert np.allclose(np.stack(got[0:3], 1), rp, rtol=0, atol=1e-13)
+    assert np.allclose(np.stack(got[3:6], 1), rv, rtol=0, atol=1e-13)
+    e = oracle.energy_view(rec, spec, blobs, n, 0.01)
+    assert e == pytest.approx(oracle.energy(rp, rv, planes[6], 0.01), rel=1e-12)
+
+
+@pytest.mark.parametrize("n,tile", [(300, 64), (257, 256), (1, 256)])
+def test_nbody_view_field_access_counts_closed_form(n, tile):
+    """Per step: each position leaf is loaded once per particle, once per particle and
+    i-block (the j-tile) and once more by the move, and stored once; velocities are
+    loaded and stored once; the mass is loaded once per particle and i-block."""
+    steps = 2
+    rec = ["f32"] * 7
+    spec = {"kind": "field_access_count", "inner": {"kind": "soa_mb"}}
+    blobs = oracle.store_planes(rec, spec["inner"], _state(n, 1, np.float32)) + [np.zeros(112, np.uint8)]
+    oracle.nbody_view(rec, spec, blobs, n, steps, 1e-4, 0.01, tile=tile)
+    got = blobs[-1].view(np.uint64).reshape(7, 2)
+    blocks = -(-n // tile)
+    want = np.zeros((7, 2), np.uint64)
+    want[0:3, 0] = steps * (n + n * blocks + n)
+    want[0:3, 1] = steps * n
+    want[3:6, :] = steps * n
+    want[6, 0] = steps * n * blocks
+    assert np.array_equal(got, want)
+    oracle.energy_view(rec, spec, blobs, n, 0.01)
+    want[:, 0] += n
+    assert np.array_equal(blobs[-1].view(np.uint64).reshape(7, 2), want)
+
+
+def test_nbody_view_heatmap_one_counter_per_element():
+    """Heatmap with 4 bytes per counter over SoA-MB f32: every counter is the number of
+    accesses (loads and stores) of its element."""
+    n, tile, steps = 130, 64, 1
+    rec = ["f32"] * 7
+    spec = {"kind": "heatmap", "granularity": 4, "inner": {"kind": "soa_mb"}}
+    blobs = oracle.store_planes(rec, spec["inner"], _state(n, 2, np.float32))
+    blobs += [np.zeros(8 * n, np.uint8) for _ in range(7)]
+    oracle.nbody_view(rec, spec, blobs, n, steps, 1e-4, 0.01, tile=tile)
+    blocks = -(-n // tile)
+    per = [1 + blocks + 2] * 3 + [2] * 3 + [blocks]
+    for f in range(7):
+        assert np.array_equal(blobs[7 + f].view(np.uint64), np.full(n, steps * per[f], np.uint64)), f
