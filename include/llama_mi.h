@@ -126,11 +126,14 @@ typedef enum llama_map_kind {
                                       < n_fields) are placed by inner[0], the
                                       rest by inner[1]: `inner` points to an
                                       array of two mappings.  Blobs: inner[0]'s,
-                                      then inner[1]'s.  On the GPU a SPLIT copies
-                                      to or from another SPLIT with the same
-                                      split point, SOA_MB or NULL, one copy per
-                                      part (UNSUPPORTED otherwise; batches take
-                                      no SPLIT or NULL views).                 */
+                                      then inner[1]'s.  Against another SPLIT
+                                      with the same split point, SOA_MB or NULL
+                                      a copy runs once per part; against any
+                                      other partner it moves each record leaf
+                                      by leaf, provided every part is physical,
+                                      a Bytesplit of one, NULL, instrumented or
+                                      a SPLIT of such (UNSUPPORTED otherwise;
+                                      batches take no SPLIT or NULL views).   */
   /* Instrumentation (Sec. 4): locations, loads and stores go to `inner`;
    * every access also adds one to 64-bit counters held in extra blobs placed
    * after the inner mapping's blobs.  The caller owns those blobs and zeroes
@@ -242,6 +245,11 @@ llama_status llama_view_records(const llama_view* view, uint64_t* n);
  * load.  AoSoA padding lanes of dst are never written.  Meta-mappings and
  * instrumentation: see LLAMA_MAP_NULL, _SPLIT, _FIELD_ACCESS_COUNT and
  * _HEATMAP (an instrumented source counts loads even into a NULL dst).
+ * Records whose leaves differ in size (Sec. 1 record dimension, e.g. the C
+ * struct {u8; f64; i16; f32}: 24-byte aligned AoS records, 15 packed) copy
+ * between the physical mappings, their Bytesplit forms and NULL, leaf by leaf;
+ * padding bytes of dst are never written.  A Bytesplit side of such a record
+ * may hold at most 64 bytes per record.
  * Errors: RECORD_MISMATCH (records or N differ), UNSUPPORTED (a pair the GPU
  * kernels do not cover; nothing is launched), INVALID_ARG. */
 llama_status llama_copy(const llama_view* src, llama_view* dst, void* stream);

@@ -761,6 +761,125 @@ llama_status plan_xpose(const llama_view* src, const llama_view* dst, Plan& plan
   return LLAMA_OK;
 }
 
+// ---------------------------------------------------------------- per-leaf copies
+
+bool mixed_record(const Rec& r) {
+  for (auto t : r)
+    if (scalar_size(t) != scalar_size(r[0])) return true;
+  return false;
+}
+
+// Adds the groups of mapping `m` over leaves [f0, f0 + rec.size()) whose blobs
+// are blobs[0 ..): a SPLIT adds one per part, an instrumented mapping its
+// inner mapping's, a physical mapping or NULL one group.
+static llama_status mix_flatten(const Rec& rec, const MapDesc& m, uint64_t n, void* const* blobs, uint32_t f0,
+                                MixSide& s, uint32_t& ng, uint32_t& ncol) {
+  const uint32_t nf = (uint32_t)rec.size();
+  switch (m.kind) {
+    case LLAMA_MAP_SPLIT: {
+      const Rec r0(rec.begin(), rec.begin() + m.lanes), r1(rec.begin() + m.lanes, rec.end());
+      llama_status st = mix_flatten(r0, *m.inner, n, blobs, f0, s, ng, ncol);
+      if (st != LLAMA_OK) return st;
+      return mix_flatten(r1, *m.inner2, n, blobs + blob_count(r0, *m.inner), f0 + m.lanes, s, ng, ncol);
+    }
+    case LLAMA_MAP_FIELD_ACCESS_COUNT:
+    case LLAMA_MAP_HEATMAP:
+      return mix_flatten(rec, *m.inner, n, blobs, f0, s, ng, ncol);
+    default:
+      break;
+  }
+  if (ng >= kMaxGroups) return fail(LLAMA_ERR_UNSUPPORTED, "more than 8 mappings in one SPLIT tree");
+  MixGroup& g = s.g[ng];
+  g = MixGroup{};
+  g.log2L = 64;
+  const MapDesc* p = &m;
+  bool bytes = false;
+  if (m.kind == LLAMA_MAP_BYTESPLIT) {
+    p = m.inner.get();
+    // over AoS the byte record's image is the packed AoS image of the leaves
+    bytes = p->kind != LLAMA_MAP_AOS;
+    if (!is_physical(p->kind)) return fail(LLAMA_ERR_UNSUPPORTED, "BYTESPLIT over a computed mapping");
+  }
+  if (m.kind == LLAMA_MAP_NULL) {
+    g.kind = MX_NULL;
+  } else if (!is_physical(p->kind)) {
+    return fail(LLAMA_ERR_UNSUPPORTED, std::string("no per-leaf copy of a ") + kind_name(m.kind) + " view");
+  } else {
+    g.kind = bytes ? MX_BYTES : MX_ELEM;
+  }
+  const bool packed = m.kind == LLAMA_MAP_BYTESPLIT || (m.flags & LLAMA_FLAG_AOS_PACKED);
+  const uint64_t P = packed_size(rec), S = (p->kind == LLAMA_MAP_AOS && !packed) ? aligned_size(rec) : P;
+  switch (p->kind) {
+    case LLAMA_MAP_AOS: g.L = 1; g.block = S; break;
+    case LLAMA_MAP_AOSOA:
+      g.L = p->lanes;
+      g.block = (uint64_t)p->lanes * P;
+      if ((p->lanes & (p->lanes - 1)) == 0) g.log2L = (uint32_t)__builtin_ctz(p->lanes);
+      break;
+    default: g.L = 0; break;  // SOA_SB, SOA_MB
+  }
+  uint64_t q = 0, po = 0;  // aligned and packed offsets of the leaf in the record
+  for (uint32_t j = 0; j < nf; ++j) {
+    const uint32_t f = f0 + j;
+    const uint64_t sz = scalar_size(rec[j]);
+    q = packed ? po : (q + sz - 1) / sz * sz;
+    s.grp[f] = (uint8_t)ng;
+    s.cidx[f] = (uint8_t)ncol;
+    if (g.kind != MX_NULL) {
+      const uint32_t cols = g.kind == MX_BYTES ? (uint32_t)sz : 1u;
+      if (ncol + cols > kMaxCols) return fail(LLAMA_ERR_UNSUPPORTED, "more than 64 storage columns in one view");
+      for (uint32_t k = 0; k < cols; ++k) {
+        const uint8_t* b = (const uint8_t*)blobs[0];
+        const uint64_t byte = po + k;  // byte column of a Bytesplit
+        switch (p->kind) {
+          case LLAMA_MAP_AOS: b += g.kind == MX_BYTES ? byte : q; break;
+          case LLAMA_MAP_SOA_SB: b += n * (g.kind == MX_BYTES ? byte : po); break;
+          case LLAMA_MAP_SOA_MB: b = (const uint8_t*)blobs[g.kind == MX_BYTES ? byte : j]; break;
+          case LLAMA_MAP_AOSOA: b += (uint64_t)g.L * (g.kind == MX_BYTES ? byte : po); break;
+          default: break;
+        }
+        s.col[ncol + k] = b;
+      }
+      if (g.kind == MX_ELEM && (uintptr_t)s.col[ncol] % sz == 0 && (g.L == 0 || g.block % sz == 0))
+        s.elem_ok |= 1ull << f;
+      ncol += cols;
+    }
+    q += sz;
+    po += sz;
+  }
+  ++ng;
+  return LLAMA_OK;
+}
+
+static llama_status mix_side(const llama_view* v, MixSide& s) {
+  std::memset(&s, 0, sizeof(s));
+  uint32_t ng = 0, ncol = 0;
+  return mix_flatten(v->rec, v->map, v->n, v->blobs.data(), 0, s, ng, ncol);
+}
+
+llama_status plan_mixed(const llama_view* src, const llama_view* dst, Plan& plan) {
+  plan = Plan{};
+  MixArgs& a = plan.ma;
+  llama_status st;
+  if ((st = mix_side(src, a.src)) != LLAMA_OK || (st = mix_side(dst, a.dst)) != LLAMA_OK) return st;
+  const uint32_t nf = (uint32_t)dst->rec.size();
+  a.n = dst->n;
+  a.nf = nf;
+  for (uint32_t f = 0; f < nf; ++f) a.lsz[f] = (uint8_t)__builtin_ctz(scalar_size(dst->rec[f]));
+  if (orders_differ(src, dst)) {
+    a.reorder = 1;
+    a.rank = dst->rank;
+    for (uint32_t d = 0; d < dst->rank; ++d) a.ext[d] = dst->extents[d];
+    a.src_col_major = src->col_major ? 1u : 0u;
+    a.dst_col_major = dst->col_major ? 1u : 0u;
+  }
+  plan.kind = PK_MIXED;
+  plan.ntiles = (dst->n + kThreads - 1) / kThreads;
+  plan.grid = (uint32_t)std::min<uint64_t>(plan.ntiles, 1u << 16);
+  plan.alg_bytes = mapped_bytes(src->rec, src->map, src->n) + mapped_bytes(dst->rec, dst->map, dst->n);
+  return LLAMA_OK;
+}
+
 llama_status launch_plan(const Plan& plan, hipStream_t st) {
   if (plan.ntiles == 0) return LLAMA_OK;
   hipError_t e = hipSuccess;
@@ -771,6 +890,7 @@ llama_status launch_plan(const Plan& plan, hipStream_t st) {
     case PK_ZERO: e = launch_zero(plan.args, plan.unit, plan.grid, st); break;
     case PK_UNPACK: e = launch_unpack(plan.args, plan.unit, plan.grid, plan.lds, st); break;
     case PK_XPOSE: e = launch_xpose(plan.xa, plan.unit, plan.grid, plan.lds, st); break;
+    case PK_MIXED: e = launch_mixed(plan.ma, plan.grid, st); break;
   }
   if (e != hipSuccess) return fail(LLAMA_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
   return LLAMA_OK;
@@ -1037,6 +1157,19 @@ static void count_steps(const llama_view* v, bool store, std::vector<CopyStep>& 
   }
 }
 
+// The counter updates of the instrumented views inside a SPLIT tree.
+static void count_parts(const llama_view* v, bool store, std::vector<CopyStep>& steps) {
+  if (instrumented(v)) {
+    count_steps(v, store, steps);
+    return;
+  }
+  if (v->map.kind != LLAMA_MAP_SPLIT) return;
+  for (int part = 0; part < 2; ++part) {
+    llama_view pv;
+    if (part_view(v, v->map.lanes, part, pv)) count_parts(&pv, store, steps);
+  }
+}
+
 // Plans a copy with the meta-mappings resolved: an instrumented view forwards
 // to its inner view and counts afterwards, a NULL destination drops the
 // values, a NULL source writes zeros, a SPLIT on either side runs one copy
@@ -1067,20 +1200,31 @@ static llama_status plan_views(const llama_view* src, const llama_view* dst, con
   // an instrumented part still counts the loads of its fields (Sec. 4).
   if (ssplit || dsplit) {
     const uint32_t k = ssplit ? src->map.lanes : dst->map.lanes;
-    for (int part = 0; part < 2; ++part) {
-      llama_view ps, pd;
-      if (!part_view(src, k, part, ps) || !part_view(dst, k, part, pd))
-        return fail(LLAMA_ERR_UNSUPPORTED,
-                    "a SPLIT view copies to or from another SPLIT with the same split point, SOA_MB or NULL");
-      llama_status s = plan_views(&ps, &pd, params, steps);
-      if (s != LLAMA_OK) return s;
+    llama_view ps[2], pd[2];
+    bool parts = true;
+    for (int part = 0; part < 2; ++part) parts = parts && part_view(src, k, part, ps[part]) && part_view(dst, k, part, pd[part]);
+    if (parts) {
+      for (int part = 0; part < 2; ++part) {
+        llama_status s = plan_views(&ps[part], &pd[part], params, steps);
+        if (s != LLAMA_OK) return s;
+      }
+      return LLAMA_OK;
     }
+    // any other partner: one per-leaf copy over both mapping trees, then the
+    // counters of their instrumented parts
+    CopyStep step;
+    llama_status s = plan_mixed(src, dst, step.plan);
+    if (s != LLAMA_OK) return s;
+    steps.push_back(step);
+    count_parts(src, false, steps);
+    count_parts(dst, true, steps);
     return LLAMA_OK;
   }
   if (dst->map.kind == LLAMA_MAP_NULL) return LLAMA_OK;
   CopyStep step;
   llama_status s;
-  if (src->map.kind == LLAMA_MAP_NULL) s = plan_zero(dst, step.plan);  // zeros in any order
+  if (mixed_record(dst->rec)) s = plan_mixed(src, dst, step.plan);  // leaves of several sizes
+  else if (src->map.kind == LLAMA_MAP_NULL) s = plan_zero(dst, step.plan);  // zeros in any order
   else if (orders_differ(src, dst)) s = plan_xpose(src, dst, step.plan);
   else s = plan_copy(src, dst, params, step.plan);
   if (s != LLAMA_OK) return s;

@@ -53,7 +53,7 @@ struct llama_view {
 
 namespace lm {
 
-enum PlanKind : uint32_t { PK_RAW = 0, PK_CONV = 1, PK_PACK = 2, PK_UNPACK = 3, PK_ZERO = 4, PK_XPOSE = 5 };
+enum PlanKind : uint32_t { PK_RAW = 0, PK_CONV = 1, PK_PACK = 2, PK_UNPACK = 3, PK_ZERO = 4, PK_XPOSE = 5, PK_MIXED = 6 };
 
 struct Plan {
   PlanKind kind = PK_RAW;
@@ -64,6 +64,7 @@ struct Plan {
   uint64_t ntiles = 0;
   TileArgs args{};
   XposeArgs xa{};  // PK_XPOSE
+  MixArgs ma{};    // PK_MIXED
 };
 
 // Builds the device description of a view.  UNSUPPORTED when the tile
@@ -95,6 +96,11 @@ void inner_view(const llama_view* v, llama_view& out);
 bool orders_differ(const llama_view* a, const llama_view* b);
 // Copy between views of different linearisation orders (same extents).
 llama_status plan_xpose(const llama_view* src, const llama_view* dst, Plan& plan);
+// True when the record's leaves are not all of one size.
+bool mixed_record(const Rec& r);
+// Per-leaf copy (records of mixed leaf sizes, SPLIT trees against any
+// partner, NULL parts), in either linearisation order.
+llama_status plan_mixed(const llama_view* src, const llama_view* dst, Plan& plan);
 
 // Geometry of one blob of a physical layout for Heatmap counting: records
 // come in periods of `period` bytes holding `recs` records each (AoS: one

@@ -140,4 +140,46 @@ struct XposeArgs {
   uint64_t mext[8], msrc[8], mdst[8];  // middle axes: extent, source and destination strides
 };
 
+// A copy that the tile engine does not cover: records whose leaves differ in
+// size (Sec. 1 record dimension, e.g. a C struct {u8; f64; i16; f32} with its
+// alignment padding), or SPLIT views (Sec. 3) with a partner of another form.
+// Each record's leaves move one element at a time, or byte by byte where a
+// side splits the leaf into byte columns or does not align it.  A side is a
+// list of groups, one per physical mapping in its mapping tree (a SPLIT has
+// one per part); leaf f belongs to group grp[f] and its element (or its first
+// byte column) is col[cidx[f]].  Record i's leaf, or byte column, c lives at
+//   col[c] + i * size                              (L = 0: planar, SoA)
+//   col[c] + (i / L) * block + (i % L) * size      (L >= 1: AoS is L = 1)
+// with size the leaf's bytes, or 1 for byte columns.
+constexpr uint32_t kMaxGroups = 8;
+enum MixKind : uint32_t { MX_ELEM = 0, MX_BYTES = 1, MX_NULL = 2 };
+
+struct MixGroup {
+  uint64_t block;  // bytes between blocks of L records
+  uint32_t L;      // records per block (0: planar)
+  uint32_t log2L;  // log2 L when L is a power of two, else 64
+  uint32_t kind;   // MixKind: whole leaves, byte columns, or NULL (loads 0, stores dropped)
+  uint32_t pad;
+};
+
+struct MixSide {
+  const uint8_t* col[kMaxCols];
+  MixGroup g[kMaxGroups];
+  uint64_t elem_ok;            // bit f: leaf f moves as one aligned element
+  uint8_t grp[kMaxFields];
+  uint8_t cidx[kMaxFields];
+};
+
+struct MixArgs {
+  MixSide src, dst;
+  uint64_t n;
+  uint32_t nf;
+  uint32_t rank;                  // extents, when the sides are linearised
+  uint32_t reorder;               //   in different orders (Sec. 2)
+  uint32_t src_col_major, dst_col_major;
+  uint32_t pad;
+  uint64_t ext[8];
+  uint8_t lsz[kMaxFields];        // log2 of each leaf's bytes
+};
+
 }  // namespace lm

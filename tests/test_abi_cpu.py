@@ -148,8 +148,9 @@ def test_copy_errors_before_gpu_work():
     assert err(lm.llama_copy_ex, a, view(F32x7, {"kind": "soa_sb"}, 100), 100) == "INVALID_ARG"
     big = view(F32x7, {"kind": "aosoa", "lanes": 4096}, 100)
     assert err(lm.llama_copy, a, big) == "UNSUPPORTED"
+    # leaves of several sizes copy per leaf, but a ChangeType needs one leaf type
     het = view(["u8", "f64"], {"kind": "aos"}, 100)
-    het2 = view(["u8", "f64"], {"kind": "soa_sb"}, 100)
+    het2 = view(["u8", "f64"], {"kind": "changetype", "stored": ["u8", "f32"], "inner": {"kind": "soa_sb"}}, 100)
     assert err(lm.llama_copy, het, het2) == "UNSUPPORTED"
     for v in (a, b, c, d, e, big, het, het2):
         lm.llama_view_destroy(v)
