@@ -517,7 +517,18 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     if (plan.args.conv == CV_NONE)
       return fail(LLAMA_ERR_UNSUPPORTED, "the GPU path converts between the float types f64, f32, f16 and bf16 only");
   }
+  // Single-blob destination planes off the 128-byte line grid: line-owner
+  // writes (every line written whole by one tile), with a halo of the
+  // records that fill the tile's last line of each plane
+  if (plan.kind == PK_RAW && D.layout == LY_PLANAR && !D.mb && D.ncols > 1 && ((D.n * D.cs) & 127u) != 0)
+    plan.args.mode = RM_LINE;
   const uint32_t mode = plan.kind == PK_RAW ? plan.args.mode : RM_DIRECT;
+  const bool line = mode == RM_LINE;
+  const uint64_t halo = line ? 128u / D.cs : 0u;
+  // records of LDS past the tile: the halo, in whole source AoSoA blocks and
+  // in multiples of 16 records (so that every LDS plane stays 16-byte aligned)
+  const uint64_t hq = S.layout == LY_AOSOA ? lcm64(16, S.lanes) : 16u;
+  const uint64_t halo_lds = line ? (halo + hq - 1u) / hq * hq : 0u;
   const bool canonical = mode == RM_MERGE || mode == RM_SPLIT;
   // canonical planar image of a relayout: element planes (MERGE) or byte planes (SPLIT)
   const uint32_t F = (uint32_t)src->rec.size(), ES = S.es;
@@ -535,7 +546,14 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
   };
   // pack: the tile's stream-word image (t * B / 8 bytes per field)
   const bool pack = plan.kind == PK_PACK;
+  // element columns split into byte planes are transposed in registers: the
+  // tile's source image is the only LDS image
+  const bool line_fused = line && S.cs == S.es && D.cs == 1 && S.es > 1;
   auto lds_total = [&](uint64_t t) -> uint64_t {
+    if (line_fused) return tile_lds_bytes(S, (uint32_t)(t + halo_lds));
+    if (line)  // the tile and its halo, verbatim and as destination planes
+      return ((tile_lds_bytes(S, (uint32_t)(t + halo_lds)) + 15u) & ~15ull) +
+             (uint64_t)D.ncols * ((t + halo_lds) * D.cs + 16u);
     const uint64_t a = tile_lds_bytes(S, (uint32_t)t);
     if (pack) return ((a + 15u) & ~15ull) + (uint64_t)D.ncols * (t * D.bits / 8u);
     if (in_place(t)) return a;
@@ -562,6 +580,8 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     const bool aos2aos = plan.kind == PK_RAW && mode == RM_DIRECT && S.layout == LY_AOS && D.layout == LY_AOS;
     const bool unpack = plan.kind == PK_UNPACK;
     const uint64_t target = pack ? 24576
+                            : line_fused ? 32768          // the tile and its halo
+                            : line ? (bd ? 40960 : 32768)  // two images of the tile and its halo
                             : unpack ? 8192
                             : plan.kind == PK_CONV ? 32768  // ChangeType: 32 KiB on the wider side
                             : aos2aos ? 7168
@@ -575,8 +595,19 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     if (k < 1) k = 1;
     const uint64_t dst_cap = unpack ? 16384 : 65536;
     while (k > 1 && (gran * k > 65536 || gran * k * dst_bytes > dst_cap)) --k;
+    if (line_fused) {
+      // a wave takes 63 windows of 16 records per field: 768 records and
+      // the halo are 57 windows, one nearly full wave group per field
+      // (measured: 768 beats 512 by 15-20 % and 1024, which needs a second,
+      // nearly empty group, by 50 %)
+      k = std::max<uint64_t>(1, 768 / gran);
+      while (k > 1 && (lds_total(gran * k) > kMaxTileLds || gran * k * dst_bytes > 65536)) --k;
+    } else if (line) {  // the largest tile whose two images (with the halo) fit the target
+      k = 1;
+      while (gran * (k + 1) <= 65536 && gran * (k + 1) * dst_bytes <= 65536 && lds_total(gran * (k + 1)) <= target) ++k;
+    }
     while (lds_cap && k > 1 && lds_total(gran * k) > lds_cap) --k;
-    if (fill && lds_cap) {  // grow the tile to the largest one within the cap
+    if (fill && lds_cap && !line) {  // grow the tile to the largest one within the cap (line tiles keep their size)
       while (gran * (k + 1) <= 65536 && lds_total(gran * (k + 1)) <= lds_cap &&
              gran * (k + 1) * dst_bytes <= 65536)
         ++k;
@@ -585,7 +616,7 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     // when a tile has 1024 or 512 records.  Measured best: 1024 when both
     // sides are byte planes and for the in-place merge into AoS, 512 for the
     // fused split and merge.
-    if (plan.kind == PK_RAW && !lds_cap && (bs || bd)) {
+    if (plan.kind == PK_RAW && !lds_cap && (bs || bd) && !line) {
       const uint64_t want = ((bs && bd) || merge_aos) ? 1024 : 512;
       uint64_t kp = std::max<uint64_t>(1, want / gran);
       while (kp > 1 && (lds_total(gran * kp) > kMaxTileLds || (merge_aos && !in_place(gran * kp)) ||
@@ -604,8 +635,9 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
   if (tile * dst_bytes > 65536)
     return fail(tile == gran ? LLAMA_ERR_UNSUPPORTED : LLAMA_ERR_INVALID_ARG,
                 "a destination tile of " + std::to_string(tile) + " records spans more than 65536 bytes");
-  S.lds_stride = lds_stride(S, (uint32_t)tile);
+  S.lds_stride = lds_stride(S, (uint32_t)(tile + halo_lds));
   D.lds_stride = lds_stride(D, (uint32_t)tile);
+  plan.args.halo = (uint32_t)halo;
   if (plan.kind == PK_RAW) {
     // destination chunks are 16-byte runs of one column when the mapping
     // keeps consecutive records of a column together
@@ -616,6 +648,20 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     std::memset(&g, 0, sizeof(g));
     if (mode == RM_DIRECT) {
       plan.args.colrun = (runs(D) && runs(S)) || (D.layout == LY_AOS && S.layout == LY_AOS);
+    } else if (line) {
+      // the destination's planes for the tile and its halo, each starting
+      // 16-byte aligned in LDS (phase 0: as for one blob per plane)
+      g.layout = LY_PLANAR;
+      g.cs = D.cs;
+      g.log2cs = log2u(D.cs);
+      g.ncols = D.ncols;
+      g.rec_bytes = D.rec_bytes;
+      g.lanes = 1;
+      g.mb = 1;
+      g.n_mod16 = 0;
+      g.lds_stride = (uint32_t)((tile + halo_lds) * D.cs + 16u);
+      g.div_L = make_div(1);
+      plan.args.can_off = (uint32_t)((tile_lds_bytes(S, (uint32_t)(tile + halo_lds)) + 15u) & ~15u);
     } else if (canonical && mode == RM_MERGE && D.layout == LY_AOS) {
       // merged straight into the destination's AoS record image
       plan.args.colrun = 1;

@@ -101,6 +101,8 @@ enum RawMode : uint32_t {
   RM_SPLIT = 2,   // Bytesplit destination: element columns split into byte planes first
   RM_MERGE_FUSED = 3,  // as RM_MERGE, transposed in registers and stored directly
   RM_SPLIT_FUSED = 4,  // as RM_SPLIT, transposed in registers and stored directly
+  RM_LINE = 5,    // single-blob planar destination off the line grid: destination
+                  // planes built in LDS, every 128-byte line written whole by one tile
 };
 
 struct TileArgs {
@@ -112,9 +114,9 @@ struct TileArgs {
   uint32_t codec;       // Codec (pack / unpack)
   uint32_t mode;        // RawMode
   uint32_t colrun;      // 1: destination chunks are runs of one column (copied 16 bytes at a time)
-  uint32_t can_off;     // LDS offset of the canonical image (MERGE / SPLIT)
-  uint32_t pad;
-  Geo can;              // canonical image geometry (MERGE / SPLIT)
+  uint32_t can_off;     // LDS offset of the canonical image (MERGE / SPLIT / LINE)
+  uint32_t halo;        // LINE: records loaded past the tile (128 / destination column bytes)
+  Geo can;              // canonical image geometry (MERGE / SPLIT / LINE)
 };
 
 // A copy between two views linearised in different orders (row- and

@@ -5,6 +5,10 @@
 namespace lm {
 
 uint32_t raw_variant(const TileArgs& a, uint32_t leaf_bytes) {
+  if (a.mode == RM_LINE) {
+    if (a.src.cs == a.dst.cs) return a.dst.cs == leaf_bytes && leaf_bytes > 1 ? RV_LINE_ES : RV_LINE_1;
+    return a.dst.cs == 1 ? RV_LINE_SPLIT : RV_LINE_MERGE;
+  }
   if (a.mode == RM_MERGE) return RV_MERGE;
   if (a.mode == RM_SPLIT) return RV_SPLIT;
   if (a.mode == RM_MERGE_FUSED) return RV_MERGE_FUSED;
@@ -20,14 +24,21 @@ static hipError_t launch_es(const TileArgs& a, uint32_t rv, uint32_t grid, uint3
     case RV_MERGE: return launch_raw_rv<ES, RV_MERGE>(a, grid, lds, st);
     case RV_SPLIT: return launch_raw_rv<ES, RV_SPLIT>(a, grid, lds, st);
     case RV_SPLIT_FUSED: return launch_raw_fused<ES, RV_SPLIT_FUSED>(a, grid, lds, st);
-    default: return launch_raw_fused<ES, RV_MERGE_FUSED>(a, grid, lds, st);
+    case RV_MERGE_FUSED: return launch_raw_fused<ES, RV_MERGE_FUSED>(a, grid, lds, st);
+    case RV_LINE_ES: return launch_raw_line<ES, RV_LINE_ES>(a, grid, lds, st);
+    case RV_LINE_1: return launch_raw_line<ES, RV_LINE_1>(a, grid, lds, st);
+    case RV_LINE_SPLIT: return launch_raw_line<ES, RV_LINE_SPLIT>(a, grid, lds, st);
+    case RV_LINE_MERGE: return launch_raw_line<ES, RV_LINE_MERGE>(a, grid, lds, st);
   }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_raw(const TileArgs& a, uint32_t leaf_bytes, uint32_t variant, uint32_t grid, uint32_t lds,
                       hipStream_t st) {
   switch (leaf_bytes) {
-    case 1: return launch_raw_rv<1, RV_DIRECT_1>(a, grid, lds, st);
+    case 1:
+      if (variant == RV_LINE_1) return launch_raw_line<1, RV_LINE_1>(a, grid, lds, st);
+      return launch_raw_rv<1, RV_DIRECT_1>(a, grid, lds, st);
     case 2: return launch_es<2>(a, variant, grid, lds, st);
     case 4: return launch_raw4(a, variant, grid, lds, st);
     case 8: return launch_es<8>(a, variant, grid, lds, st);

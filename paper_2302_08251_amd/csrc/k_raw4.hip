@@ -10,8 +10,13 @@ hipError_t launch_raw4(const TileArgs& a, uint32_t variant, uint32_t grid, uint3
     case RV_MERGE: return launch_raw_rv<4, RV_MERGE>(a, grid, lds, st);
     case RV_SPLIT: return launch_raw_rv<4, RV_SPLIT>(a, grid, lds, st);
     case RV_SPLIT_FUSED: return launch_raw_fused<4, RV_SPLIT_FUSED>(a, grid, lds, st);
-    default: return launch_raw_fused<4, RV_MERGE_FUSED>(a, grid, lds, st);
+    case RV_MERGE_FUSED: return launch_raw_fused<4, RV_MERGE_FUSED>(a, grid, lds, st);
+    case RV_LINE_ES: return launch_raw_line<4, RV_LINE_ES>(a, grid, lds, st);
+    case RV_LINE_1: return launch_raw_line<4, RV_LINE_1>(a, grid, lds, st);
+    case RV_LINE_SPLIT: return launch_raw_line<4, RV_LINE_SPLIT>(a, grid, lds, st);
+    case RV_LINE_MERGE: return launch_raw_line<4, RV_LINE_MERGE>(a, grid, lds, st);
   }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace lm

@@ -28,7 +28,18 @@ enum RawVariant : uint32_t {
   RV_SPLIT = 3,      // element columns -> Bytesplit destination
   RV_SPLIT_FUSED = 4,  // RV_SPLIT without the canonical image
   RV_MERGE_FUSED = 5,  // RV_MERGE without the canonical image
+  // line-owner writes into single-blob planes off the line grid (RM_LINE),
+  // by how the destination planes are built:
+  RV_LINE_ES = 6,      //   element columns on both sides
+  RV_LINE_1 = 7,       //   byte columns on both sides
+  RV_LINE_SPLIT = 8,   //   element columns -> byte planes, transposed in registers
+  RV_LINE_MERGE = 9,   //   byte columns -> element planes
 };
+
+template <int RV>
+constexpr bool is_line_variant() {
+  return RV == RV_LINE_ES || RV == RV_LINE_1 || RV == RV_LINE_SPLIT || RV == RV_LINE_MERGE;
+}
 
 // Phase B for one destination layout DL from an LDS image of layout SL, with
 // the item loop form FORM (see load_tile).
@@ -52,6 +63,24 @@ __device__ __forceinline__ void tile_raw_sl(const TileArgs& a, uint64_t i0, uint
   // Phase B, and in Phase A when the source is one segment (AoS, AoSoA)
   constexpr int FORM_A = RV == RV_DIRECT_ES && (SL == LY_AOS || SL == LY_AOSOA) ? 1 : 0;
   constexpr int FORM_B = RV == RV_DIRECT_ES ? 1 : 0;
+  if constexpr (is_line_variant<RV>()) {
+    // the tile and its halo: the records up to the end of the tile's last line
+    const uint64_t left = a.src.n - i0;
+    const uint32_t nl = left < (uint64_t)(nt + a.halo) ? (uint32_t)left : nt + a.halo;
+    load_tile<SL, 0>(a.src, i0, nl, lds);
+    wait_tile_loads();
+    if constexpr (RV == RV_LINE_SPLIT) {
+      store_split_lines16<ES, SL>(a.src, a.dst, i0, nt, nl, lds);
+      return;
+    }
+    uint8_t* can = lds + a.can_off;
+    if constexpr (RV == RV_LINE_ES) relayout_plain<ES, SL>(a.src, nl, lds, can, a.can);
+    else if constexpr (RV == RV_LINE_1) relayout_plain<1, SL>(a.src, nl, lds, can, a.can);
+    else relayout_merge<ES, SL>(a.src, nl, lds, can, a.can);
+    __syncthreads();
+    store_lines<(RV == RV_LINE_ES || RV == RV_LINE_MERGE) ? ES : 1>(a.can, a.dst, i0, nt, nl, can);
+    return;
+  }
   load_tile<SL, FORM_A>(a.src, i0, nt, lds);
   wait_tile_loads();
   if constexpr (RV == RV_SPLIT_FUSED) {
@@ -84,7 +113,7 @@ __device__ __forceinline__ void tile_raw_sl(const TileArgs& a, uint64_t i0, uint
 // any physical layout.
 template <int ES, int RV, int DL, int COLRUN>
 __device__ __forceinline__ void tile_raw(const TileArgs& a, uint64_t i0, uint32_t nt, uint8_t* lds) {
-  if constexpr (RV == RV_MERGE || RV == RV_MERGE_FUSED) {
+  if constexpr (RV == RV_MERGE || RV == RV_MERGE_FUSED || RV == RV_LINE_MERGE) {
     if (a.src.layout == LY_AOSOA) tile_raw_sl<ES, RV, DL, COLRUN, LY_AOSOA>(a, i0, nt, lds);
     else tile_raw_sl<ES, RV, DL, COLRUN, LY_PLANAR>(a, i0, nt, lds);
   } else {
@@ -113,8 +142,14 @@ __device__ __forceinline__ void tile_raw_any(const TileArgs& a, uint32_t rv, uin
     else tile_raw<ES, RV, LY_PLANAR, 0>(a, i0, nt, lds);                     \
     return;                                                                  \
   }
+#define LM_RVL(RV) \
+  if (rv == RV) {                                                            \
+    tile_raw<ES, RV, LY_PLANAR, 0>(a, i0, nt, lds);                          \
+    return;                                                                  \
+  }
   if constexpr (ES == 1) {
     LM_RV(RV_DIRECT_1)
+    LM_RVL(RV_LINE_1)
   } else {
     LM_RV(RV_DIRECT_ES)
     LM_RV(RV_DIRECT_1)
@@ -122,7 +157,12 @@ __device__ __forceinline__ void tile_raw_any(const TileArgs& a, uint32_t rv, uin
     LM_RV(RV_SPLIT)
     LM_RVF(RV_SPLIT_FUSED)
     LM_RVF(RV_MERGE_FUSED)
+    LM_RVL(RV_LINE_ES)
+    LM_RVL(RV_LINE_1)
+    LM_RVL(RV_LINE_SPLIT)
+    LM_RVL(RV_LINE_MERGE)
   }
+#undef LM_RVL
 #undef LM_RVF
 #undef LM_RV
 #undef LM_DL
@@ -217,6 +257,12 @@ template <int ES, int RV>
 inline hipError_t launch_raw_fused(const TileArgs& a, uint32_t grid, uint32_t lds, hipStream_t st) {
   if (a.dst.layout == LY_AOSOA) hipLaunchKernelGGL((k_raw<ES, RV, LY_AOSOA, 0>), dim3(grid), dim3(kThreads), lds, st, a);
   else hipLaunchKernelGGL((k_raw<ES, RV, LY_PLANAR, 0>), dim3(grid), dim3(kThreads), lds, st, a);
+  return hipGetLastError();
+}
+
+template <int ES, int RV>
+inline hipError_t launch_raw_line(const TileArgs& a, uint32_t grid, uint32_t lds, hipStream_t st) {
+  hipLaunchKernelGGL((k_raw<ES, RV, LY_PLANAR, 0>), dim3(grid), dim3(kThreads), lds, st, a);
   return hipGetLastError();
 }
 

@@ -655,6 +655,102 @@ __device__ __forceinline__ void store_identity(const G& s, const Side& d, uint64
 }
 
 // ---------------------------------------------------------------------------
+// Line-owner Phase B for single-blob planar destinations whose planes start
+// off the 128-byte line grid (n * column bytes not a multiple of 128).  When
+// two workgroups each write part of one line, the memory system merges the
+// parts by a read-modify-write of the line; with planes off the grid every
+// tile boundary of every plane would cost one.  Here each line of a plane is
+// written whole by exactly one tile: the tile owns the plane's bytes from the
+// first line boundary at or after its first record to the first one at or
+// after its end (the plane's own start and end bound the first and last
+// tile).  Its last line reaches up to 128 / cs records into the next tile,
+// so the tile loads that many more records (the halo).  The destination's
+// planes are built in a canonical LDS image whose planes start 16-byte
+// aligned, so the relayout writes whole aligned dwords (a plane phased like
+// the destination would turn them into byte writes); each 16-byte chunk is
+// then realigned on the way out from two aligned 16-byte LDS reads (one
+// funnel shift, its offset uniform per plane) and leaves as one 128-bit
+// store.  Only lines shared by the end of one plane and the start of the
+// next keep two writers.
+// ---------------------------------------------------------------------------
+
+// Canonical planes (column size U) from a source image whose columns are U
+// bytes too: plane c holds column c of records 0 .. nl - 1.
+template <int U, int SL>
+__device__ __forceinline__ void relayout_plain(const Side& s, uint32_t nl, const uint8_t* lds, uint8_t* can,
+                                               const Geo& cg) {
+  const uint32_t C = s.ncols;
+  const uint32_t quads = (nl + 3u) >> 2;
+  const Div dq = make_div_dev(quads);
+  const uint32_t items = C * quads;
+  for (uint32_t q = threadIdx.x; q < items; q += blockDim.x) {
+    const uint32_t c = fdiv(q, dq);
+    const uint32_t r = (q - c * quads) * 4u;
+    if constexpr (U == 1) {
+      const uint32_t v = read_run4<SL>(s, lds, r, c);
+      lds_write<4>(can, c * cg.lds_stride + planar_phase(cg, c) + r, &v);
+    } else {
+      uint32_t e[U];
+      read_elems4<U, SL>(s, lds, r, c, e);
+      lds_write<4 * U>(can, c * cg.lds_stride + planar_phase(cg, c) + r * U, e);
+    }
+  }
+}
+
+__device__ __forceinline__ u32x4 funnel16(const u32x4& p, const u32x4& o, uint32_t ph);
+
+template <int U>
+__device__ __forceinline__ void store_lines(const Geo& cg, const Side& d, uint64_t i0, uint32_t nt, uint32_t nl,
+                                            const uint8_t* can) {
+  const uint32_t w = wave_id(), nw = num_waves(), lane = lane_id();
+  const uint64_t plane = d.n * U;                              // bytes per plane
+  const uint32_t gps = (nl * U + 32u + 1023u) >> 10;          // groups of 64 chunks per plane (upper bound)
+  const Div dg = make_div_dev(gps);
+  const uint32_t items = d.ncols * gps;
+  const bool first = i0 == 0, last = i0 + nt >= d.n;
+  for (uint32_t it = w; it < items; it += nw) {
+    const uint32_t c = fdiv(it, dg);
+    const uint32_t grp = it - c * gps;
+    const uint64_t p0 = plane * c, pe = p0 + plane;            // the plane in the blob
+    const uint64_t t0 = p0 + i0 * U;                           // the tile's first record
+    const uint64_t te = t0 + (uint64_t)nt * U;
+    const uint64_t b0 = first ? t0 : (t0 + 127u) & ~127ull;    // owned bytes [b0, b1)
+    uint64_t b1 = last ? pe : (te + 127u) & ~127ull;
+    if (b1 > pe) b1 = pe;
+    const uint64_t abase = b0 & ~15ull;
+    const auto rs = make_rsrc((const uint8_t*)d.blob[0] + abase, d.blob_size - abase);
+    const uint32_t chunk = grp * 64u + lane;
+    const uint64_t g = abase + chunk * 16ull;                  // the chunk in the blob
+    if (g >= b1) continue;
+    // the chunk's first byte in the canonical plane (aligned plane start;
+    // a mod 16 is the same for every chunk of the plane)
+    const uint32_t a = c * cg.lds_stride + (uint32_t)(g - t0);
+    if (g >= b0 && g + 16u <= b1) {
+      const uint32_t k = a & 15u;
+      u32x4 v;
+      if (k == 0u) {
+        v = *(const u32x4*)(can + a);
+      } else {  // two aligned reads, inside the plane's 16 bytes of slack
+        const u32x4 p = *(const u32x4*)(can + (a - k)), o = *(const u32x4*)(can + (a - k) + 16u);
+        v = funnel16(p, o, 16u - k);
+      }
+      __builtin_amdgcn_raw_buffer_store_b128(v, rs, chunk * 16u, 0, kStoreNT);
+    } else {
+#pragma unroll
+      for (uint32_t u = 0; u < 16u / U; ++u) {
+        const uint64_t gb = g + u * U;
+        if (gb < b0 || gb >= b1) continue;
+        const uint32_t o = chunk * 16u + u * U, la = a + u * U;
+        if constexpr (U == 1) __builtin_amdgcn_raw_buffer_store_b8(can[la], rs, o, 0, 0);
+        else if constexpr (U == 2) __builtin_amdgcn_raw_buffer_store_b16(*(const uint16_t*)(can + la), rs, o, 0, 0);
+        else if constexpr (U == 4) __builtin_amdgcn_raw_buffer_store_b32(*(const uint32_t*)(can + la), rs, o, 0, 0);
+        else __builtin_amdgcn_raw_buffer_store_b64(*(const u32x2*)(can + la), rs, o, 0, 0);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Fused relayout + store for Bytesplit pairs whose byte runs stay 4-byte
 // aligned.  Work items are (field f, 64 blocks of 4 records); the field is
 // wave-uniform, so every byte column a wave writes has a uniform buffer
@@ -880,6 +976,91 @@ __device__ __forceinline__ void store_split_fused16(const Side& s, const Side& d
         // the tile's last run: its last ph bytes have no owner in this tile
         if (writer && q + 1u == runs)
           for (uint32_t j = lead; j < nrec; ++j) __builtin_amdgcn_raw_buffer_store_b8(own_byte(j), rs, lo + j, 0, 0);
+      }
+    }
+  }
+}
+
+// The 16-byte split with line-owner writes (single-blob byte planes off the
+// line grid, see store_lines): the tile's source image holds its records and
+// the halo (nl records), lanes take runs of 16 records of one field as in
+// store_split_fused16, and the 16-byte window that starts ph bytes before a
+// lane's run (ph = the plane's phase mod 16) is written when it lies inside
+// the bytes the tile owns in that plane.  Window w joins the last ph bytes of
+// run w - 1 (the left neighbour's) and the first 16 - ph bytes of run w; lane
+// 0 of each wave only supplies its run to lane 1, and one window past the
+// last run carries that run's last ph bytes.  No byte is written twice and
+// every owned line is written whole; only the planes' ends use byte stores.
+template <int ES, int SL>
+__device__ __forceinline__ void store_split_lines16(const Side& s, const Side& d, uint64_t i0, uint32_t nt,
+                                                    uint32_t nl, const uint8_t* lds) {
+  const uint32_t F = s.ncols;
+  const uint32_t runs = (nl + 15u) >> 4;
+  const uint32_t wins = runs + 1u;
+  const uint32_t gpf = (wins + 62u) / 63u;
+  const uint32_t w0 = wave_id(), nw = num_waves(), lane = lane_id();
+  const Div dg = make_div_dev(gpf);
+  const uint32_t items = F * gpf;
+  const bool first = i0 == 0, last = i0 + nt >= d.n;
+  for (uint32_t it = w0; it < items; it += nw) {
+    const uint32_t f = fdiv(it, dg);
+    const int qi = (int)((it - f * gpf) * 63u + lane) - 1;
+    const bool has = qi >= 0 && qi < (int)runs;  // a run of the tile's image
+    const uint32_t q = qi >= 0 ? (uint32_t)qi : 0u;  // the lane's run and window
+    const bool writer = lane != 0u && qi >= 0 && qi < (int)wins;
+    const uint32_t r = has ? q * 16u : 0u;
+    uint32_t col[ES][4];  // col[k][m]: byte k of records r + 4m .. r + 4m + 3
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      uint32_t e[ES];
+      read_elems4<ES, SL>(s, lds, r + 4u * m, f, e);
+      if constexpr (ES == 2) {
+        col[0][m] = __builtin_amdgcn_perm(e[1], e[0], 0x06040200u);
+        col[1][m] = __builtin_amdgcn_perm(e[1], e[0], 0x07050301u);
+      } else {
+        constexpr int DW = ES / 4;
+#pragma unroll
+        for (int h = 0; h < DW; ++h) {
+          uint32_t in[4], o[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) in[j] = e[j * DW + h];
+          transpose4x4(in, o);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) col[4 * h + k][m] = o[k];
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < ES; ++k) {
+      const uint32_t c = f * ES + k;
+      const uint64_t p0 = d.n * c, pe = p0 + d.n;  // byte plane c in the blob
+      const uint64_t t0 = p0 + i0, te = t0 + nt;
+      const uint64_t b0 = first ? t0 : (t0 + 127u) & ~127ull;
+      uint64_t b1 = last ? pe : (te + 127u) & ~127ull;
+      if (b1 > pe) b1 = pe;
+      const uint32_t ph = (uint32_t)t0 & 15u;  // wave-uniform
+      const u32x4 own = has ? u32x4{col[k][0], col[k][1], col[k][2], col[k][3]} : u32x4{0u, 0u, 0u, 0u};
+      const int src_lane = (int)((lane ? lane - 1u : 0u) * 4u);
+      const u32x4 prev = u32x4{(uint32_t)__builtin_amdgcn_ds_bpermute(src_lane, (int)own.x),
+                               (uint32_t)__builtin_amdgcn_ds_bpermute(src_lane, (int)own.y),
+                               (uint32_t)__builtin_amdgcn_ds_bpermute(src_lane, (int)own.z),
+                               (uint32_t)__builtin_amdgcn_ds_bpermute(src_lane, (int)own.w)};
+      if (!writer) continue;
+      const uint64_t ws = t0 + 16ull * q - ph;  // the window, 16-byte aligned
+      if (ws >= b1 || ws + 16u <= b0) continue;
+      const uint64_t base = ws & ~127ull;
+      const auto rs = make_rsrc((const uint8_t*)d.blob[0] + base, d.blob_size - base);
+      const uint32_t lo = (uint32_t)(ws - base);
+      if (ws >= b0 && ws + 16u <= b1) {
+        __builtin_amdgcn_raw_buffer_store_b128(ph ? funnel16(prev, own, ph) : own, rs, lo, 0, kStoreNT);
+      } else {
+        for (uint32_t j = 0; j < 16u; ++j) {
+          const uint64_t gb = ws + j;
+          if (gb < b0 || gb >= b1) continue;
+          const uint32_t b = j < ph ? 16u - ph + j : j - ph;  // byte of the neighbour's run, or of the own run
+          const u32x4& src = j < ph ? prev : own;
+          __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(src[b >> 2] >> (8u * (b & 3u))), rs, lo + j, 0, 0);
+        }
       }
     }
   }
