@@ -32,6 +32,7 @@ struct llama_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<Plan> pv;
+  std::vector<BatchGroup> groups;  // views by leaf size: one kernel each
 };
 
 namespace {
@@ -58,11 +59,12 @@ void release_device(llama_batch* b) {
 // that the persistent workgroups, which walk the tile space in order, keep
 // one variant's code hot at a time.
 llama_status build_items(llama_batch* b, uint32_t T, std::vector<BatchItem>& items, std::vector<uint32_t>& prefix,
-                         uint32_t& lds) {
+                         uint32_t& lds, std::vector<BatchGroup>* groups = nullptr) {
   const size_t n = b->srcs.size();
   std::vector<BatchItem> plans(n);
   std::vector<uint64_t> tiles(n);
   std::vector<uint64_t> key(n);
+  std::vector<uint32_t> plan_lds(n);
   // T = 2: every view's tile grown to the LDS that the largest default tile
   // needs (one launch allocates that much for every workgroup anyway)
   uint32_t fill_cap = 0;
@@ -91,6 +93,7 @@ llama_status build_items(llama_batch* b, uint32_t T, std::vector<BatchItem>& ite
     key[v] = ((uint64_t)p.unit << 40) | ((uint64_t)plans[v].variant << 32) | ((uint64_t)p.args.dst.layout << 24) |
              ((uint64_t)p.args.src.layout << 16) | ((uint64_t)p.args.colrun << 8);
     lds = std::max(lds, p.lds);
+    plan_lds[v] = p.lds;
   }
   std::vector<size_t> order(n);
   for (size_t v = 0; v < n; ++v) order[v] = v;
@@ -104,16 +107,43 @@ llama_status build_items(llama_batch* b, uint32_t T, std::vector<BatchItem>& ite
     if (total >= 0x80000000ull) return fail(LLAMA_ERR_INDEX_OVERFLOW, "batch has too many tiles");
     prefix[k + 1] = (uint32_t)total;
   }
+  if (groups) {  // runs of one leaf size (the sort key's top field)
+    groups->clear();
+    for (size_t k = 0; k < n; ++k) {
+      if (groups->empty() || groups->back().unit != items[k].unit)
+        groups->push_back(BatchGroup{items[k].unit, prefix[k], prefix[k], (uint32_t)k, (uint32_t)k, 0u});
+      BatchGroup& g = groups->back();
+      g.t_end = prefix[k + 1];
+      g.v_end = (uint32_t)k + 1;
+      g.lds = std::max(g.lds, plan_lds[order[k]]);
+    }
+  }
   return LLAMA_OK;
+}
+
+// One launch per leaf-size group; a persistent grid G is shared out by the
+// groups' tile counts, and G >= the batch's tiles means one workgroup per tile.
+hipError_t launch_groups(const llama_batch* b, uint32_t G, hipStream_t st) {
+  for (const BatchGroup& g : b->groups) {
+    const uint64_t nt = g.t_end - g.t_begin;
+    if (nt == 0) continue;
+    uint64_t gg = G >= b->total_tiles ? nt : (G * nt + b->total_tiles - 1) / b->total_tiles;
+    gg = std::max<uint64_t>(1, std::min<uint64_t>(gg, nt));
+    hipError_t e = launch_batch(b->d_items, b->d_prefix, b->d_tile_view, g, (uint32_t)gg, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 llama_status upload(llama_batch* b, uint32_t T) {
   std::vector<BatchItem> items;
   std::vector<uint32_t> prefix;
   uint32_t lds;
-  llama_status st = build_items(b, T, items, prefix, lds);
+  std::vector<BatchGroup> groups;
+  llama_status st = build_items(b, T, items, prefix, lds, &groups);
   if (st != LLAMA_OK) return st;
   release_device(b);
+  b->groups = groups;
   hipError_t e;
   if ((e = hipMalloc(&b->d_items, items.size() * sizeof(BatchItem))) != hipSuccess) return hip_fail(e, "hipMalloc");
   if ((e = hipMalloc(&b->d_prefix, prefix.size() * sizeof(uint32_t))) != hipSuccess) return hip_fail(e, "hipMalloc");
@@ -147,7 +177,7 @@ llama_status capture(llama_batch* b) {
   b->graph = nullptr;
   if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
     return hip_fail(e, "hipStreamBeginCapture");
-  hipError_t le = launch_batch(b->d_items, b->d_prefix, b->d_tile_view, (uint32_t)b->total_tiles, (uint32_t)b->srcs.size(), b->grid, b->lds, b->cap);
+  hipError_t le = launch_groups(b, b->grid, b->cap);
   e = hipStreamEndCapture(b->cap, &b->graph);
   if (le != hipSuccess) return hip_fail(le, "batched launch");
   if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
@@ -284,7 +314,7 @@ llama_status autotune(llama_batch* b, uint64_t granule, uint32_t& bestT, uint32_
           1, std::min<uint64_t>(mult ? (uint64_t)cus * mult : b->total_tiles, b->total_tiles));
       hipError_t le = hipSuccess;
       auto run = [&]() {
-        hipError_t e = launch_batch(b->d_items, b->d_prefix, b->d_tile_view, (uint32_t)b->total_tiles, (uint32_t)b->srcs.size(), G, b->lds, b->cap);
+        hipError_t e = launch_groups(b, G, b->cap);
         if (e != hipSuccess) le = e;
       };
       run();

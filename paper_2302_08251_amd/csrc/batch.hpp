@@ -13,8 +13,19 @@ struct BatchItem {
   uint32_t pad[2];
 };
 
-// tile_view: view index of every tile (total_tiles entries), or null
+// The views of one leaf size (contiguous after the host's ordering) and
+// their tiles [t_begin, t_end) of the batch's tile space: one kernel, compiled
+// for that leaf size only, moves them.
+struct BatchGroup {
+  uint32_t unit;              // leaf bytes
+  uint32_t t_begin, t_end;    // tiles
+  uint32_t v_begin, v_end;    // views
+  uint32_t lds;               // the largest LDS of the group's views
+};
+
+// tile_view: view index of every tile of the batch, or null (then each
+// workgroup searches the prefix sums)
 hipError_t launch_batch(const BatchItem* items, const uint32_t* prefix, const uint32_t* tile_view,
-                        uint32_t total_tiles, uint32_t n_views, uint32_t grid, uint32_t lds, hipStream_t st);
+                        const BatchGroup& g, uint32_t grid, hipStream_t st);
 
 }  // namespace lm

@@ -546,11 +546,13 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
   };
   // pack: the tile's stream-word image (t * B / 8 bytes per field)
   const bool pack = plan.kind == PK_PACK;
-  // element columns split into byte planes are transposed in registers: the
-  // tile's source image is the only LDS image
-  const bool line_fused = line && S.cs == S.es && D.cs == 1 && S.es > 1;
+  // Line-owner copies read the destination's columns straight from the
+  // tile's source image (the only LDS image), except byte columns merged into
+  // element planes, which go through a canonical image of those planes
+  const bool line_fused = line && !(S.cs == 1 && D.cs > 1);
   auto lds_total = [&](uint64_t t) -> uint64_t {
-    if (line_fused) return tile_lds_bytes(S, (uint32_t)(t + halo_lds));
+    // (+16: a misaligned byte-column read fetches the dword after the last plane)
+    if (line_fused) return tile_lds_bytes(S, (uint32_t)(t + halo_lds)) + 16u;
     if (line)  // the tile and its halo, verbatim and as destination planes
       return ((tile_lds_bytes(S, (uint32_t)(t + halo_lds)) + 15u) & ~15ull) +
              (uint64_t)D.ncols * ((t + halo_lds) * D.cs + 16u);
@@ -580,7 +582,7 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     const bool aos2aos = plan.kind == PK_RAW && mode == RM_DIRECT && S.layout == LY_AOS && D.layout == LY_AOS;
     const bool unpack = plan.kind == PK_UNPACK;
     const uint64_t target = pack ? 24576
-                            : line_fused ? 32768          // the tile and its halo
+                            : line_fused ? (D.cs == 1 && S.cs > 1 ? 32768 : 24576)  // the tile and its halo
                             : line ? (bd ? 40960 : 32768)  // two images of the tile and its halo
                             : unpack ? 8192
                             : plan.kind == PK_CONV ? 32768  // ChangeType: 32 KiB on the wider side
@@ -596,12 +598,27 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     const uint64_t dst_cap = unpack ? 16384 : 65536;
     while (k > 1 && (gran * k > 65536 || gran * k * dst_bytes > dst_cap)) --k;
     if (line_fused) {
-      // a wave takes 63 windows of 16 records per field: 768 records and
-      // the halo are 57 windows, one nearly full wave group per field
-      // (measured: 768 beats 512 by 15-20 % and 1024, which needs a second,
-      // nearly empty group, by 50 %)
-      k = std::max<uint64_t>(1, 768 / gran);
-      while (k > 1 && (lds_total(gran * k) > kMaxTileLds || gran * k * dst_bytes > 65536)) --k;
+      // A wave writes 63 windows of 16 bytes of one destination column per
+      // step (16 / cs records each; the tile and its halo, plus one window).
+      // Take the tile within the LDS target whose windows fill their wave
+      // steps best, weighed by the share of the loads the halo adds
+      // (measured for the split: 768 records, 57 windows, beat 512 by
+      // 15-20 % and 1024, whose second step is nearly empty, by 50 %).
+      const uint64_t R = 16u / D.cs;
+      double best = -1.0;
+      uint64_t bk = 1;
+      for (uint64_t kk = 1; gran * kk <= 4096; ++kk) {
+        const uint64_t t = gran * kk;
+        if ((kk > 1 && lds_total(t) > target) || lds_total(t) > kMaxTileLds || t * dst_bytes > 65536) break;
+        const uint64_t wins = (t + halo + R - 1u) / R + 1u;
+        const uint64_t steps = (wins + 62u) / 63u;
+        const double score = (double)wins / (63.0 * (double)steps) * (double)t / (double)(t + halo);
+        if (score > best + 1e-9) {
+          best = score;
+          bk = kk;
+        }
+      }
+      k = bk;
     } else if (line) {  // the largest tile whose two images (with the halo) fit the target
       k = 1;
       while (gran * (k + 1) <= 65536 && gran * (k + 1) * dst_bytes <= 65536 && lds_total(gran * (k + 1)) <= target) ++k;

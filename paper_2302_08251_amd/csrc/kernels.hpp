@@ -71,14 +71,16 @@ __device__ __forceinline__ void tile_raw_sl(const TileArgs& a, uint64_t i0, uint
     wait_tile_loads();
     if constexpr (RV == RV_LINE_SPLIT) {
       store_split_lines16<ES, SL>(a.src, a.dst, i0, nt, nl, lds);
-      return;
+    } else if constexpr (RV == RV_LINE_ES) {
+      store_plain_lines16<ES, SL>(a.src, a.dst, i0, nt, nl, lds);
+    } else if constexpr (RV == RV_LINE_1) {
+      store_plain_lines16<1, SL>(a.src, a.dst, i0, nt, nl, lds);
+    } else {  // byte columns merged into element planes through a canonical image
+      uint8_t* can = lds + a.can_off;
+      relayout_merge<ES, SL>(a.src, nl, lds, can, a.can);
+      __syncthreads();
+      store_lines<ES>(a.can, a.dst, i0, nt, nl, can);
     }
-    uint8_t* can = lds + a.can_off;
-    if constexpr (RV == RV_LINE_ES) relayout_plain<ES, SL>(a.src, nl, lds, can, a.can);
-    else if constexpr (RV == RV_LINE_1) relayout_plain<1, SL>(a.src, nl, lds, can, a.can);
-    else relayout_merge<ES, SL>(a.src, nl, lds, can, a.can);
-    __syncthreads();
-    store_lines<(RV == RV_LINE_ES || RV == RV_LINE_MERGE) ? ES : 1>(a.can, a.dst, i0, nt, nl, can);
     return;
   }
   load_tile<SL, FORM_A>(a.src, i0, nt, lds);

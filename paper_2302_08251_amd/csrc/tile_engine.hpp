@@ -674,29 +674,6 @@ __device__ __forceinline__ void store_identity(const G& s, const Side& d, uint64
 // next keep two writers.
 // ---------------------------------------------------------------------------
 
-// Canonical planes (column size U) from a source image whose columns are U
-// bytes too: plane c holds column c of records 0 .. nl - 1.
-template <int U, int SL>
-__device__ __forceinline__ void relayout_plain(const Side& s, uint32_t nl, const uint8_t* lds, uint8_t* can,
-                                               const Geo& cg) {
-  const uint32_t C = s.ncols;
-  const uint32_t quads = (nl + 3u) >> 2;
-  const Div dq = make_div_dev(quads);
-  const uint32_t items = C * quads;
-  for (uint32_t q = threadIdx.x; q < items; q += blockDim.x) {
-    const uint32_t c = fdiv(q, dq);
-    const uint32_t r = (q - c * quads) * 4u;
-    if constexpr (U == 1) {
-      const uint32_t v = read_run4<SL>(s, lds, r, c);
-      lds_write<4>(can, c * cg.lds_stride + planar_phase(cg, c) + r, &v);
-    } else {
-      uint32_t e[U];
-      read_elems4<U, SL>(s, lds, r, c, e);
-      lds_write<4 * U>(can, c * cg.lds_stride + planar_phase(cg, c) + r * U, e);
-    }
-  }
-}
-
 __device__ __forceinline__ u32x4 funnel16(const u32x4& p, const u32x4& o, uint32_t ph);
 
 template <int U>
@@ -1061,6 +1038,82 @@ __device__ __forceinline__ void store_split_lines16(const Side& s, const Side& d
           const u32x4& src = j < ph ? prev : own;
           __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(src[b >> 2] >> (8u * (b & 3u))), rs, lo + j, 0, 0);
         }
+      }
+    }
+  }
+}
+
+// Line-owner writes of columns that keep their size (element planes from
+// element columns, byte planes from byte columns): as store_split_lines16,
+// with a lane's run being 16 bytes of one column (16 / U records) read
+// straight from the tile's source image.
+template <int U, int SL>
+__device__ __forceinline__ u32x4 read_col16(const Side& s, const uint8_t* lds, uint32_t r, uint32_t c) {
+  if constexpr (U == 1) {
+    return u32x4{read_run4<SL>(s, lds, r, c), read_run4<SL>(s, lds, r + 4u, c), read_run4<SL>(s, lds, r + 8u, c),
+                 read_run4<SL>(s, lds, r + 12u, c)};
+  } else if constexpr (U == 2) {
+    uint32_t e0[2], e1[2];
+    read_elems4<2, SL>(s, lds, r, c, e0);
+    read_elems4<2, SL>(s, lds, r + 4u, c, e1);
+    return u32x4{e0[0], e0[1], e1[0], e1[1]};
+  } else if constexpr (U == 4) {
+    uint32_t e[4];
+    read_elems4<4, SL>(s, lds, r, c, e);
+    return u32x4{e[0], e[1], e[2], e[3]};
+  } else {
+    const u32x2 a = *(const u32x2*)(lds + src_addr<SL>(s, r, c * 8u));
+    const u32x2 b = *(const u32x2*)(lds + src_addr<SL>(s, r + 1u, c * 8u));
+    return u32x4{a.x, a.y, b.x, b.y};
+  }
+}
+
+template <int U, int SL>
+__device__ __forceinline__ void store_plain_lines16(const Side& s, const Side& d, uint64_t i0, uint32_t nt,
+                                                    uint32_t nl, const uint8_t* lds) {
+  constexpr uint32_t R = 16u / U;  // records per run
+  const uint32_t C = s.ncols;
+  const uint32_t runs = (nl + R - 1u) / R;
+  const uint32_t wins = runs + 1u;
+  const uint32_t gpf = (wins + 62u) / 63u;
+  const uint32_t w0 = wave_id(), nw = num_waves(), lane = lane_id();
+  const Div dg = make_div_dev(gpf);
+  const uint32_t items = C * gpf;
+  const bool first = i0 == 0, last = i0 + nt >= d.n;
+  const uint64_t plane = d.n * U;
+  for (uint32_t it = w0; it < items; it += nw) {
+    const uint32_t c = fdiv(it, dg);
+    const int qi = (int)((it - c * gpf) * 63u + lane) - 1;
+    const bool has = qi >= 0 && qi < (int)runs;
+    const uint32_t q = qi >= 0 ? (uint32_t)qi : 0u;
+    const bool writer = lane != 0u && qi >= 0 && qi < (int)wins;
+    const u32x4 own = has ? read_col16<U, SL>(s, lds, q * R, c) : u32x4{0u, 0u, 0u, 0u};
+    const uint64_t p0 = plane * c, pe = p0 + plane;
+    const uint64_t t0 = p0 + i0 * U, te = t0 + (uint64_t)nt * U;
+    const uint64_t b0 = first ? t0 : (t0 + 127u) & ~127ull;
+    uint64_t b1 = last ? pe : (te + 127u) & ~127ull;
+    if (b1 > pe) b1 = pe;
+    const uint32_t ph = (uint32_t)t0 & 15u;  // wave-uniform
+    const int src_lane = (int)((lane ? lane - 1u : 0u) * 4u);
+    const u32x4 prev = u32x4{(uint32_t)__builtin_amdgcn_ds_bpermute(src_lane, (int)own.x),
+                             (uint32_t)__builtin_amdgcn_ds_bpermute(src_lane, (int)own.y),
+                             (uint32_t)__builtin_amdgcn_ds_bpermute(src_lane, (int)own.z),
+                             (uint32_t)__builtin_amdgcn_ds_bpermute(src_lane, (int)own.w)};
+    if (!writer) continue;
+    const uint64_t ws = t0 + 16ull * q - ph;
+    if (ws >= b1 || ws + 16u <= b0) continue;
+    const uint64_t base = ws & ~127ull;
+    const auto rs = make_rsrc((const uint8_t*)d.blob[0] + base, d.blob_size - base);
+    const uint32_t lo = (uint32_t)(ws - base);
+    if (ws >= b0 && ws + 16u <= b1) {
+      __builtin_amdgcn_raw_buffer_store_b128(ph ? funnel16(prev, own, ph) : own, rs, lo, 0, kStoreNT);
+    } else {
+      for (uint32_t j = 0; j < 16u; ++j) {
+        const uint64_t gb = ws + j;
+        if (gb < b0 || gb >= b1) continue;
+        const uint32_t b = j < ph ? 16u - ph + j : j - ph;
+        const u32x4& src = j < ph ? prev : own;
+        __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(src[b >> 2] >> (8u * (b & 3u))), rs, lo + j, 0, 0);
       }
     }
   }
