@@ -546,16 +546,11 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
   };
   // pack: the tile's stream-word image (t * B / 8 bytes per field)
   const bool pack = plan.kind == PK_PACK;
-  // Line-owner copies read the destination's columns straight from the
-  // tile's source image (the only LDS image), except byte columns merged into
-  // element planes, which go through a canonical image of those planes
-  const bool line_fused = line && !(S.cs == 1 && D.cs > 1);
   auto lds_total = [&](uint64_t t) -> uint64_t {
-    // (+16: a misaligned byte-column read fetches the dword after the last plane)
-    if (line_fused) return tile_lds_bytes(S, (uint32_t)(t + halo_lds)) + 16u;
-    if (line)  // the tile and its halo, verbatim and as destination planes
-      return ((tile_lds_bytes(S, (uint32_t)(t + halo_lds)) + 15u) & ~15ull) +
-             (uint64_t)D.ncols * ((t + halo_lds) * D.cs + 16u);
+    // line-owner copies build the destination's runs in registers from the
+    // tile's source image (and halo), the only LDS image (+16: a misaligned
+    // byte-column read fetches the dword after the last plane)
+    if (line) return tile_lds_bytes(S, (uint32_t)(t + halo_lds)) + 16u;
     const uint64_t a = tile_lds_bytes(S, (uint32_t)t);
     if (pack) return ((a + 15u) & ~15ull) + (uint64_t)D.ncols * (t * D.bits / 8u);
     if (in_place(t)) return a;
@@ -582,8 +577,7 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     const bool aos2aos = plan.kind == PK_RAW && mode == RM_DIRECT && S.layout == LY_AOS && D.layout == LY_AOS;
     const bool unpack = plan.kind == PK_UNPACK;
     const uint64_t target = pack ? 24576
-                            : line_fused ? (D.cs == 1 && S.cs > 1 ? 32768 : 24576)  // the tile and its halo
-                            : line ? (bd ? 40960 : 32768)  // two images of the tile and its halo
+                            : line ? (D.cs == 1 && S.cs > 1 ? 32768 : 24576)  // the tile and its halo
                             : unpack ? 8192
                             : plan.kind == PK_CONV ? 32768  // ChangeType: 32 KiB on the wider side
                             : aos2aos ? 7168
@@ -597,7 +591,7 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     if (k < 1) k = 1;
     const uint64_t dst_cap = unpack ? 16384 : 65536;
     while (k > 1 && (gran * k > 65536 || gran * k * dst_bytes > dst_cap)) --k;
-    if (line_fused) {
+    if (line) {
       // A wave writes 63 windows of 16 bytes of one destination column per
       // step (16 / cs records each; the tile and its halo, plus one window).
       // Take the tile within the LDS target whose windows fill their wave
@@ -619,9 +613,6 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
         }
       }
       k = bk;
-    } else if (line) {  // the largest tile whose two images (with the halo) fit the target
-      k = 1;
-      while (gran * (k + 1) <= 65536 && gran * (k + 1) * dst_bytes <= 65536 && lds_total(gran * (k + 1)) <= target) ++k;
     }
     while (lds_cap && k > 1 && lds_total(gran * k) > lds_cap) --k;
     if (fill && lds_cap && !line) {  // grow the tile to the largest one within the cap (line tiles keep their size)
@@ -665,20 +656,6 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     std::memset(&g, 0, sizeof(g));
     if (mode == RM_DIRECT) {
       plan.args.colrun = (runs(D) && runs(S)) || (D.layout == LY_AOS && S.layout == LY_AOS);
-    } else if (line) {
-      // the destination's planes for the tile and its halo, each starting
-      // 16-byte aligned in LDS (phase 0: as for one blob per plane)
-      g.layout = LY_PLANAR;
-      g.cs = D.cs;
-      g.log2cs = log2u(D.cs);
-      g.ncols = D.ncols;
-      g.rec_bytes = D.rec_bytes;
-      g.lanes = 1;
-      g.mb = 1;
-      g.n_mod16 = 0;
-      g.lds_stride = (uint32_t)((tile + halo_lds) * D.cs + 16u);
-      g.div_L = make_div(1);
-      plan.args.can_off = (uint32_t)((tile_lds_bytes(S, (uint32_t)(tile + halo_lds)) + 15u) & ~15u);
     } else if (canonical && mode == RM_MERGE && D.layout == LY_AOS) {
       // merged straight into the destination's AoS record image
       plan.args.colrun = 1;

@@ -72,14 +72,14 @@ __device__ __forceinline__ void tile_raw_sl(const TileArgs& a, uint64_t i0, uint
     if constexpr (RV == RV_LINE_SPLIT) {
       store_split_lines16<ES, SL>(a.src, a.dst, i0, nt, nl, lds);
     } else if constexpr (RV == RV_LINE_ES) {
-      store_plain_lines16<ES, SL>(a.src, a.dst, i0, nt, nl, lds);
+      store_lines16<ES>(a.dst, i0, nt, nl, a.src.ncols,
+                        [&](uint32_t r, uint32_t c) { return read_col16<ES, SL>(a.src, lds, r, c); });
     } else if constexpr (RV == RV_LINE_1) {
-      store_plain_lines16<1, SL>(a.src, a.dst, i0, nt, nl, lds);
-    } else {  // byte columns merged into element planes through a canonical image
-      uint8_t* can = lds + a.can_off;
-      relayout_merge<ES, SL>(a.src, nl, lds, can, a.can);
-      __syncthreads();
-      store_lines<ES>(a.can, a.dst, i0, nt, nl, can);
+      store_lines16<1>(a.dst, i0, nt, nl, a.src.ncols,
+                       [&](uint32_t r, uint32_t c) { return read_col16<1, SL>(a.src, lds, r, c); });
+    } else {  // byte columns merged into element planes
+      store_lines16<ES>(a.dst, i0, nt, nl, a.src.ncols / ES,
+                        [&](uint32_t r, uint32_t f) { return read_merge16<ES, SL>(a.src, lds, r, f); });
     }
     return;
   }

@@ -664,68 +664,14 @@ __device__ __forceinline__ void store_identity(const G& s, const Side& d, uint64
 // first line boundary at or after its first record to the first one at or
 // after its end (the plane's own start and end bound the first and last
 // tile).  Its last line reaches up to 128 / cs records into the next tile,
-// so the tile loads that many more records (the halo).  The destination's
-// planes are built in a canonical LDS image whose planes start 16-byte
-// aligned, so the relayout writes whole aligned dwords (a plane phased like
-// the destination would turn them into byte writes); each 16-byte chunk is
-// then realigned on the way out from two aligned 16-byte LDS reads (one
-// funnel shift, its offset uniform per plane) and leaves as one 128-bit
-// store.  Only lines shared by the end of one plane and the start of the
-// next keep two writers.
+// so the tile loads that many more records (the halo).  Lanes build 16-byte
+// runs of one destination column in registers straight from the tile's
+// source image and write 16-byte windows aligned to the destination, each
+// joining the left neighbour's run and the lane's own (store_lines16,
+// store_split_lines16).  Only lines shared by the end of one plane and the
+// start of the next keep two writers.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ u32x4 funnel16(const u32x4& p, const u32x4& o, uint32_t ph);
-
-template <int U>
-__device__ __forceinline__ void store_lines(const Geo& cg, const Side& d, uint64_t i0, uint32_t nt, uint32_t nl,
-                                            const uint8_t* can) {
-  const uint32_t w = wave_id(), nw = num_waves(), lane = lane_id();
-  const uint64_t plane = d.n * U;                              // bytes per plane
-  const uint32_t gps = (nl * U + 32u + 1023u) >> 10;          // groups of 64 chunks per plane (upper bound)
-  const Div dg = make_div_dev(gps);
-  const uint32_t items = d.ncols * gps;
-  const bool first = i0 == 0, last = i0 + nt >= d.n;
-  for (uint32_t it = w; it < items; it += nw) {
-    const uint32_t c = fdiv(it, dg);
-    const uint32_t grp = it - c * gps;
-    const uint64_t p0 = plane * c, pe = p0 + plane;            // the plane in the blob
-    const uint64_t t0 = p0 + i0 * U;                           // the tile's first record
-    const uint64_t te = t0 + (uint64_t)nt * U;
-    const uint64_t b0 = first ? t0 : (t0 + 127u) & ~127ull;    // owned bytes [b0, b1)
-    uint64_t b1 = last ? pe : (te + 127u) & ~127ull;
-    if (b1 > pe) b1 = pe;
-    const uint64_t abase = b0 & ~15ull;
-    const auto rs = make_rsrc((const uint8_t*)d.blob[0] + abase, d.blob_size - abase);
-    const uint32_t chunk = grp * 64u + lane;
-    const uint64_t g = abase + chunk * 16ull;                  // the chunk in the blob
-    if (g >= b1) continue;
-    // the chunk's first byte in the canonical plane (aligned plane start;
-    // a mod 16 is the same for every chunk of the plane)
-    const uint32_t a = c * cg.lds_stride + (uint32_t)(g - t0);
-    if (g >= b0 && g + 16u <= b1) {
-      const uint32_t k = a & 15u;
-      u32x4 v;
-      if (k == 0u) {
-        v = *(const u32x4*)(can + a);
-      } else {  // two aligned reads, inside the plane's 16 bytes of slack
-        const u32x4 p = *(const u32x4*)(can + (a - k)), o = *(const u32x4*)(can + (a - k) + 16u);
-        v = funnel16(p, o, 16u - k);
-      }
-      __builtin_amdgcn_raw_buffer_store_b128(v, rs, chunk * 16u, 0, kStoreNT);
-    } else {
-#pragma unroll
-      for (uint32_t u = 0; u < 16u / U; ++u) {
-        const uint64_t gb = g + u * U;
-        if (gb < b0 || gb >= b1) continue;
-        const uint32_t o = chunk * 16u + u * U, la = a + u * U;
-        if constexpr (U == 1) __builtin_amdgcn_raw_buffer_store_b8(can[la], rs, o, 0, 0);
-        else if constexpr (U == 2) __builtin_amdgcn_raw_buffer_store_b16(*(const uint16_t*)(can + la), rs, o, 0, 0);
-        else if constexpr (U == 4) __builtin_amdgcn_raw_buffer_store_b32(*(const uint32_t*)(can + la), rs, o, 0, 0);
-        else __builtin_amdgcn_raw_buffer_store_b64(*(const u32x2*)(can + la), rs, o, 0, 0);
-      }
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Fused relayout + store for Bytesplit pairs whose byte runs stay 4-byte
@@ -1068,11 +1014,51 @@ __device__ __forceinline__ u32x4 read_col16(const Side& s, const uint8_t* lds, u
   }
 }
 
-template <int U, int SL>
-__device__ __forceinline__ void store_plain_lines16(const Side& s, const Side& d, uint64_t i0, uint32_t nt,
-                                                    uint32_t nl, const uint8_t* lds) {
+// 16 bytes of element column f (16 / ES records from r) merged from the ES
+// byte columns of a Bytesplit source image.
+template <int ES, int SL>
+__device__ __forceinline__ u32x4 read_merge16(const Side& s, const uint8_t* lds, uint32_t r, uint32_t f) {
+  if constexpr (ES == 2) {
+    uint32_t o[4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t b0 = read_run4<SL>(s, lds, r + 4u * h, 2 * f), b1 = read_run4<SL>(s, lds, r + 4u * h, 2 * f + 1);
+      o[2 * h] = __builtin_amdgcn_perm(b1, b0, 0x05010400u);
+      o[2 * h + 1] = __builtin_amdgcn_perm(b1, b0, 0x07030602u);
+    }
+    return u32x4{o[0], o[1], o[2], o[3]};
+  } else {
+    // byte runs come in aligned groups of 4 records: merge the group that
+    // holds records r, r + 1 (ES = 8) or r .. r + 3 (ES = 4), keep 16 bytes
+    constexpr int DW = ES / 4;
+    const uint32_t r4 = r & ~3u;
+    uint32_t out[ES];
+#pragma unroll
+    for (int h = 0; h < DW; ++h) {
+      uint32_t in[4], o[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) in[k] = read_run4<SL>(s, lds, r4, f * ES + 4 * h + k);
+      transpose4x4(in, o);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) out[j * DW + h] = o[j];
+    }
+    if constexpr (ES == 8) {
+      if (r != r4) return u32x4{out[4], out[5], out[6], out[7]};
+    }
+    return u32x4{out[0], out[1], out[2], out[3]};
+  }
+}
+
+// Line-owner writes of destination columns of U bytes (see store_lines): a
+// lane's run is 16 bytes of one column (16 / U records), given by read(r, c);
+// the 16-byte window starting ph bytes before it joins the left neighbour's
+// last ph bytes and the run's first 16 - ph bytes, and is written when it
+// lies in the bytes the tile owns.  Lane 0 of each wave only supplies its
+// run; one window past the last run carries that run's last ph bytes.
+template <int U, typename Read>
+__device__ __forceinline__ void store_lines16(const Side& d, uint64_t i0, uint32_t nt, uint32_t nl, uint32_t C,
+                                              Read&& read) {
   constexpr uint32_t R = 16u / U;  // records per run
-  const uint32_t C = s.ncols;
   const uint32_t runs = (nl + R - 1u) / R;
   const uint32_t wins = runs + 1u;
   const uint32_t gpf = (wins + 62u) / 63u;
@@ -1087,7 +1073,7 @@ __device__ __forceinline__ void store_plain_lines16(const Side& s, const Side& d
     const bool has = qi >= 0 && qi < (int)runs;
     const uint32_t q = qi >= 0 ? (uint32_t)qi : 0u;
     const bool writer = lane != 0u && qi >= 0 && qi < (int)wins;
-    const u32x4 own = has ? read_col16<U, SL>(s, lds, q * R, c) : u32x4{0u, 0u, 0u, 0u};
+    const u32x4 own = has ? read(q * R, c) : u32x4{0u, 0u, 0u, 0u};
     const uint64_t p0 = plane * c, pe = p0 + plane;
     const uint64_t t0 = p0 + i0 * U, te = t0 + (uint64_t)nt * U;
     const uint64_t b0 = first ? t0 : (t0 + 127u) & ~127ull;
