@@ -520,6 +520,7 @@ def bench_cfg4(lm, torch, reps, count):
            "speedup": float(np.median(tv) / np.median(tb)), "tile_records": info["tile_records"],
            "grid": info["grid"], "total_tiles": info["total_tiles"],
            "persistent_grid": bool(info["grid"] < info["total_tiles"]),
+           "xcd_contiguous_tiles": bool(info["tile_map"]),
            "records_per_s": float(ns.sum()) / (np.median(tb) * 1e-3),
            "tune_seconds": info["tune_seconds"], "create_seconds": create_s, "parity_gate": "round trip via SoA-MB"}
     batch.close()

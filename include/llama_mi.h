@@ -306,6 +306,9 @@ typedef struct llama_batch_info {
   uint64_t total_tiles;
   uint64_t algorithmic_bytes;/* mapped bytes read + mapped bytes written       */
   double tune_seconds;       /* wall time spent autotuning at create (0 = cached) */
+  uint32_t tile_map;         /* 1: one workgroup per tile, each of the 8 XCDs taking a
+                                contiguous run of tiles (chosen by the autotuner) */
+  uint32_t reserved;
 } llama_batch_info;
 llama_status llama_batch_get_info(const llama_batch* batch, llama_batch_info* info);
 llama_status llama_batch_destroy(llama_batch* batch);

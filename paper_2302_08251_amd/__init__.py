@@ -73,7 +73,7 @@ class LaunchParams(C.Structure):
 class BatchInfo(C.Structure):
     _fields_ = [("n_views", C.c_uint32), ("tile_records", C.c_uint32), ("grid", C.c_uint32),
                 ("total_tiles", C.c_uint64), ("algorithmic_bytes", C.c_uint64),
-                ("tune_seconds", C.c_double)]
+                ("tune_seconds", C.c_double), ("tile_map", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 _lib = None

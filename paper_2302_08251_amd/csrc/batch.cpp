@@ -23,6 +23,7 @@ struct llama_batch {
   std::vector<const llama_view*> srcs;
   std::vector<llama_view*> dsts;
   uint32_t tile = 0, grid = 0, lds = 0, pv_tile = 0;
+  uint32_t tile_map = 0;  // 1: one workgroup per tile, each XCD taking a contiguous run of tiles
   uint64_t total_tiles = 0, alg_bytes = 0;
   double tune_seconds = 0;
   BatchItem* d_items = nullptr;
@@ -111,7 +112,7 @@ llama_status build_items(llama_batch* b, uint32_t T, std::vector<BatchItem>& ite
     groups->clear();
     for (size_t k = 0; k < n; ++k) {
       if (groups->empty() || groups->back().unit != items[k].unit)
-        groups->push_back(BatchGroup{items[k].unit, prefix[k], prefix[k], (uint32_t)k, (uint32_t)k, 0u});
+        groups->push_back(BatchGroup{items[k].unit, prefix[k], prefix[k], (uint32_t)k, (uint32_t)k, 0u, 0u});
       BatchGroup& g = groups->back();
       g.t_end = prefix[k + 1];
       g.v_end = (uint32_t)k + 1;
@@ -122,9 +123,11 @@ llama_status build_items(llama_batch* b, uint32_t T, std::vector<BatchItem>& ite
 }
 
 // One launch per leaf-size group; a persistent grid G is shared out by the
-// groups' tile counts, and G >= the batch's tiles means one workgroup per tile.
-hipError_t launch_groups(const llama_batch* b, uint32_t G, hipStream_t st) {
-  for (const BatchGroup& g : b->groups) {
+// groups' tile counts, and G >= the batch's tiles means one workgroup per
+// tile (then M = 1 gives each XCD a contiguous run of the group's tiles).
+hipError_t launch_groups(const llama_batch* b, uint32_t G, uint32_t M, hipStream_t st) {
+  for (BatchGroup g : b->groups) {
+    g.tile_map = M;
     const uint64_t nt = g.t_end - g.t_begin;
     if (nt == 0) continue;
     uint64_t gg = G >= b->total_tiles ? nt : (G * nt + b->total_tiles - 1) / b->total_tiles;
@@ -177,7 +180,7 @@ llama_status capture(llama_batch* b) {
   b->graph = nullptr;
   if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
     return hip_fail(e, "hipStreamBeginCapture");
-  hipError_t le = launch_groups(b, b->grid, b->cap);
+  hipError_t le = launch_groups(b, b->grid, b->tile_map, b->cap);
   e = hipStreamEndCapture(b->cap, &b->graph);
   if (le != hipSuccess) return hip_fail(le, "batched launch");
   if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
@@ -253,7 +256,7 @@ std::string device_key(const llama_batch* b) {
   return buf;
 }
 
-bool cache_lookup(const char* path, const std::string& key, uint32_t& T, uint32_t& G, uint32_t& P) {
+bool cache_lookup(const char* path, const std::string& key, uint32_t& T, uint32_t& G, uint32_t& P, uint32_t& M) {
   std::ifstream f(path);
   if (!f) return false;
   std::stringstream ss;
@@ -261,18 +264,20 @@ bool cache_lookup(const char* path, const std::string& key, uint32_t& T, uint32_
   const std::string s = ss.str();
   const size_t k = s.find("\"" + key + "\"");
   if (k == std::string::npos) return false;
+  const size_t end = s.find('\n', k);  // the entry's own line
   auto num = [&](const char* name, uint32_t& out) {
     size_t p = s.find(std::string("\"") + name + "\"", k);
-    if (p == std::string::npos) return false;
+    if (p == std::string::npos || p > end) return false;
     p = s.find(':', p);
     if (p == std::string::npos) return false;
     out = (uint32_t)std::strtoul(s.c_str() + p + 1, nullptr, 10);
     return true;
   };
-  return num("tile_records", T) && num("grid", G) && num("per_view_tile", P) && G > 0;
+  if (!num("tile_map", M)) M = 0;
+  return num("tile_records", T) && num("grid", G) && num("per_view_tile", P) && G > 0 && M <= 1;
 }
 
-void cache_store(const char* path, const std::string& key, uint32_t T, uint32_t G, uint32_t P) {
+void cache_store(const char* path, const std::string& key, uint32_t T, uint32_t G, uint32_t P, uint32_t M) {
   // keep the other entries: the file holds one entry per line
   std::vector<std::string> lines;
   {
@@ -285,8 +290,9 @@ void cache_store(const char* path, const std::string& key, uint32_t T, uint32_t 
       }
   }
   char buf[512];
-  std::snprintf(buf, sizeof(buf), "  \"%s\": {\"tile_records\": %u, \"grid\": %u, \"per_view_tile\": %u}",
-                key.c_str(), T, G, P);
+  std::snprintf(buf, sizeof(buf),
+                "  \"%s\": {\"tile_records\": %u, \"grid\": %u, \"per_view_tile\": %u, \"tile_map\": %u}",
+                key.c_str(), T, G, P, M);
   lines.push_back(buf);
   std::ofstream o(path, std::ios::trunc);
   if (!o) return;
@@ -295,7 +301,8 @@ void cache_store(const char* path, const std::string& key, uint32_t T, uint32_t 
   o << "}\n";
 }
 
-llama_status autotune(llama_batch* b, uint64_t granule, uint32_t& bestT, uint32_t& bestG, uint32_t& bestP) {
+llama_status autotune(llama_batch* b, uint64_t granule, uint32_t& bestT, uint32_t& bestG, uint32_t& bestP,
+                      uint32_t& bestM) {
   int dev = 0, cus = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -306,15 +313,20 @@ llama_status autotune(llama_batch* b, uint64_t granule, uint32_t& bestT, uint32_
   for (uint32_t T : {512u, 1024u})
     if (T % granule == 0) tiles.push_back(T);
   double best = 1e30, best_pv = 1e30;
-  bestT = bestG = bestP = 0;
+  bestT = bestG = bestP = bestM = 0;
   for (uint32_t T : tiles) {
     if (upload(b, T) != LLAMA_OK) continue;  // e.g. a tile that does not fit in LDS
-    for (uint32_t mult : {8u, 32u, 128u, 0u}) {  // 0: one workgroup per tile
+    // grids of 8, 32, 128 workgroups per CU, or one per tile (0), that one
+    // also with each XCD taking a contiguous run of tiles (neighbouring
+    // tiles then share lines in one L2)
+    const uint32_t cands[5][2] = {{8u, 0u}, {32u, 0u}, {128u, 0u}, {0u, 0u}, {0u, 1u}};
+    for (const auto& cm : cands) {
+      const uint32_t mult = cm[0], M = cm[1];
       const uint32_t G = (uint32_t)std::max<uint64_t>(
           1, std::min<uint64_t>(mult ? (uint64_t)cus * mult : b->total_tiles, b->total_tiles));
       hipError_t le = hipSuccess;
       auto run = [&]() {
-        hipError_t e = launch_groups(b, G, b->cap);
+        hipError_t e = launch_groups(b, G, M, b->cap);
         if (e != hipSuccess) le = e;
       };
       run();
@@ -324,6 +336,7 @@ llama_status autotune(llama_batch* b, uint64_t granule, uint32_t& bestT, uint32_
         best = ms;
         bestT = T;
         bestG = G;
+        bestM = M;
       }
     }
     std::vector<Plan> pv;
@@ -376,9 +389,9 @@ llama_status llama_batch_create(uint32_t n, const llama_view* const* srcs, llama
   e = hipStreamCreate(&b->cap);
   if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
   const std::string key = device_key(b.get());
-  uint32_t T = 0, G = 0, P = 0;
+  uint32_t T = 0, G = 0, P = 0, M = 0;
   llama_status st;
-  const bool cached = tune_cache && cache_lookup(tune_cache, key, T, G, P);
+  const bool cached = tune_cache && cache_lookup(tune_cache, key, T, G, P, M);
   // a cached entry whose tile sizes no longer plan for these views (for
   // example a tile that does not fit the LDS of wider leaves) is tuned anew
   bool usable = cached;
@@ -392,15 +405,16 @@ llama_status llama_batch_create(uint32_t n, const llama_view* const* srcs, llama
   }
   if (!usable) {
     const auto t0 = std::chrono::steady_clock::now();
-    if ((st = autotune(b.get(), granule, T, G, P)) != LLAMA_OK) {
+    if ((st = autotune(b.get(), granule, T, G, P, M)) != LLAMA_OK) {
       release_device(b.get());
       (void)hipStreamDestroy(b->cap);
       return st;
     }
     b->tune_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    if (tune_cache) cache_store(tune_cache, key, T, G, P);
+    if (tune_cache) cache_store(tune_cache, key, T, G, P, M);
   }
   b->grid = G;
+  b->tile_map = M;
   b->pv_tile = P;
   (void)hipStreamSynchronize(b->cap);
   st = upload(b.get(), T);
@@ -446,6 +460,8 @@ llama_status llama_batch_get_info(const llama_batch* b, llama_batch_info* info) 
   info->total_tiles = b->total_tiles;
   info->algorithmic_bytes = b->alg_bytes;
   info->tune_seconds = b->tune_seconds;
+  info->tile_map = b->tile_map;
+  info->reserved = 0;
   return LLAMA_OK;
 }
 

@@ -21,6 +21,7 @@ struct BatchGroup {
   uint32_t t_begin, t_end;    // tiles
   uint32_t v_begin, v_end;    // views
   uint32_t lds;               // the largest LDS of the group's views
+  uint32_t tile_map;          // 1: each XCD takes a contiguous run of the group's tiles
 };
 
 // tile_view: view index of every tile of the batch, or null (then each

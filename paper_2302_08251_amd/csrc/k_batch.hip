@@ -17,7 +17,10 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchItem* __restrict_
                                                    const uint32_t* __restrict__ tile_view, const BatchGroup g) {
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   uint32_t v = g.v_begin;
-  for (uint32_t t = g.t_begin + blockIdx.x; t < g.t_end; t += gridDim.x) {
+  const uint32_t nt_all = g.t_end - g.t_begin;
+  const bool xmap = g.tile_map && gridDim.x >= nt_all;
+  for (uint32_t b = blockIdx.x; b < nt_all; b += gridDim.x) {
+    const uint32_t t = g.t_begin + (xmap ? xcd_tile(b, nt_all) : b);
     // view holding tile t: prefix[v] <= t < prefix[v + 1].  With one
     // workgroup per tile the host's tile -> view table answers in one load;
     // a persistent workgroup visits its tiles in increasing order and

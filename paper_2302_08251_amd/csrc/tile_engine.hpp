@@ -36,6 +36,15 @@ __device__ __forceinline__ uint32_t wave_id() {
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
 __device__ __forceinline__ uint32_t num_waves() { return blockDim.x >> 6; }
 
+// The tile of workgroup b (of n, one per tile) when each of the 8 XCDs takes
+// a contiguous run of the tiles: workgroup b runs on XCD b mod 8, so
+// neighbouring tiles share that XCD's L2 (lines they both touch are fetched
+// from HBM once).
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n) {
+  const uint32_t x = b & 7u, k = b >> 3, q = n >> 3, r = n & 7u;
+  return x * q + (x < r ? x : r) + k;
+}
+
 __device__ __forceinline__ uint32_t fdiv(uint32_t x, const Div& d) {
   return d.pow2 ? (x >> d.sh) : __umulhi(x, d.m);
 }

@@ -107,6 +107,30 @@ def test_batch_every_tile_choice_matches_oracle(tmp_path, code, grid):
     b.close()
 
 
+@pytest.mark.parametrize("tile_map", [0, 1])
+def test_batch_xcd_tile_map_matches_oracle(tmp_path, tile_map):
+    """One workgroup per tile, with and without each XCD taking a contiguous
+    run of tiles (forced through the tune cache), over mixed mapping pairs."""
+    torch = pytest.importorskip("torch")
+    views = make_batch(40, 1, 30000, seed=8)
+    path = tmp_path / "tune.json"
+    b0 = lm.Batch([v[0] for v in views], [v[1] for v in views], tune_cache=str(path))
+    b0.close()
+    import re
+    text = re.sub(r'"grid": \d+', '"grid": %d' % (1 << 30), path.read_text())
+    text = re.sub(r'"tile_map": \d+', '"tile_map": %d' % tile_map, text)
+    path.write_text(text)
+    b = lm.Batch([v[0] for v in views], [v[1] for v in views], tune_cache=str(path))
+    info = b.info()
+    say("tile map", tile_map, info)
+    assert info["tile_map"] == tile_map and info["grid"] == info["total_tiles"]
+    reset(views)
+    b.launch()
+    torch.cuda.synchronize()
+    check(views, "tile map %d" % tile_map)
+    b.close()
+
+
 def test_batch_mixed_record_types_matches_oracle():
     """One launch over views of different leaf sizes (f64, f32, i16, u8 records)
     and mappings, Bytesplit included; every view equals the oracle's copy."""
