@@ -223,10 +223,13 @@ __global__ __launch_bounds__(kThreads) void k_tile(const TileArgs a) {
     const uint64_t left = a.src.n - i0;
     const uint32_t nt = left < (uint64_t)a.tile ? (uint32_t)left : a.tile;
     // pack: the stream-word image of the tile (one plane of tile * B / 32
-    // words per field) follows the source image in LDS
+    // words per field) follows the source image in LDS (can_off 0: none, every
+    // field's codes are stored from registers)
     uint32_t* words = (uint32_t*)(lds + a.can_off);
     const uint32_t wstride = (a.tile * a.dst.bits) >> 5;
-    if constexpr (KIND == 2) pack_clear_words(words, a.dst.ncols * wstride);
+    if constexpr (KIND == 2) {
+      if (a.can_off) pack_clear_words(words, a.dst.ncols * wstride);  // 0: no word image
+    }
     if constexpr (KIND == 3) load_tile<LY_STREAM>(a.src, i0, nt, lds);
     else load_tile(a.src, i0, nt, lds);
     wait_tile_loads();

@@ -1679,6 +1679,93 @@ __device__ __forceinline__ void or_bits(uint32_t* wf, uint32_t bit, uint32_t cod
     __hip_atomic_fetch_or(wf + w + 1u, code >> (32u - sh), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// The NWQ = B / 8 stream words that four consecutive B-bit codes fill
+// exactly (B = 8, 16, 24, 32), in stream order.
+template <int NWQ>
+__device__ __forceinline__ void pack_quad_words(const uint32_t (&c)[4], uint32_t (&w)[4]) {
+  if constexpr (NWQ == 1) {
+    w[0] = c[0] | (c[1] << 8) | (c[2] << 16) | (c[3] << 24);
+  } else if constexpr (NWQ == 2) {
+    w[0] = c[0] | (c[1] << 16);
+    w[1] = c[2] | (c[3] << 16);
+  } else if constexpr (NWQ == 3) {
+    w[0] = c[0] | (c[1] << 24);
+    w[1] = (c[1] >> 8) | (c[2] << 16);
+    w[2] = (c[2] >> 16) | (c[3] << 8);
+  } else {
+    w[0] = c[0]; w[1] = c[1]; w[2] = c[2]; w[3] = c[3];
+  }
+}
+
+// Codes of a plane of 4-byte values straight from registers to the stream
+// (B = 8 * NWQ): a lane encodes four consecutive values from one 16-byte LDS
+// read and stores their NWQ whole words, so a wave writes 64 * NWQ * 4
+// contiguous bytes per store.  Full quads need no checks; the tile's last,
+// partial quad is written by one lane, word by word up to the stream's end.
+template <int NWQ, int CODEC, int FMT>
+__device__ __forceinline__ void pack_direct(const uint8_t* plane, uint32_t nt, uint32_t nw,
+                                            __amdgpu_buffer_rsrc_t rs, const Side& d) {
+  const uint32_t full = nt >> 2;
+#pragma unroll 2
+  for (uint32_t q = threadIdx.x; q < full; q += blockDim.x) {
+    const u32x4 v = *(const u32x4*)(plane + 16u * q);
+    uint32_t c[4], w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[k] = encode_fmt<CODEC, FMT>(v[k], d);
+    pack_quad_words<NWQ>(c, w);
+    const uint32_t off = 4u * NWQ * q;  // the quad's first word
+    if constexpr (NWQ == 1) __builtin_amdgcn_raw_buffer_store_b32(w[0], rs, off, 0, kStoreNT);
+    else if constexpr (NWQ == 2) __builtin_amdgcn_raw_buffer_store_b64(u32x2{w[0], w[1]}, rs, off, 0, kStoreNT);
+    else if constexpr (NWQ == 3) __builtin_amdgcn_raw_buffer_store_b96(u32x3{w[0], w[1], w[2]}, rs, off, 0, kStoreNT);
+    else __builtin_amdgcn_raw_buffer_store_b128(u32x4{w[0], w[1], w[2], w[3]}, rs, off, 0, kStoreNT);
+  }
+  if ((nt & 3u) && threadIdx.x == 0) {
+    const u32x4 v = *(const u32x4*)(plane + 16u * full);
+    uint32_t c[4], w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[k] = 4u * full + k < nt ? encode_fmt<CODEC, FMT>(v[k], d) : 0u;
+    pack_quad_words<NWQ>(c, w);
+    for (uint32_t k = 0; k < (uint32_t)NWQ && NWQ * full + k < nw; ++k)
+      __builtin_amdgcn_raw_buffer_store_b32(w[k], rs, 4u * (NWQ * full + k), 0, 0);
+  }
+}
+
+// Codes of a plane of 4-byte values into the tile's stream-word image, four
+// consecutive values per lane.  CLS 0: B = 8, 16 or 32 (whole words, plain
+// LDS stores); CLS 1: B < 8 (the four codes as one group); CLS 2: B < 16 (two
+// pairs); CLS 3: B < 32 (one by one).  Groups that may share a word with
+// another lane's are ORed in with LDS atomics (a group spans at most two
+// words).  Values past the tile give code 0.
+template <int CLS, int CODEC, int FMT>
+__device__ __forceinline__ void pack_image(const uint8_t* plane, uint32_t nt, uint32_t B, uint32_t* wf,
+                                           const Side& d) {
+  const uint32_t quads = (nt + 3u) >> 2;
+  for (uint32_t q = threadIdx.x; q < quads; q += blockDim.x) {
+    const u32x4 v = *(const u32x4*)(plane + 16u * q);
+    const uint32_t r = 4u * q;
+    uint32_t c[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[k] = encode_fmt<CODEC, FMT>(v[k], d);
+    if (r + 4u > nt) {
+#pragma unroll
+      for (int k = 1; k < 4; ++k) c[k] = r + k < nt ? c[k] : 0u;
+    }
+    if constexpr (CLS == 0) {
+      if (B == 8u) wf[q] = c[0] | (c[1] << 8) | (c[2] << 16) | (c[3] << 24);
+      else if (B == 16u) *(u32x2*)(wf + 2u * q) = u32x2{c[0] | (c[1] << 16), c[2] | (c[3] << 16)};
+      else *(u32x4*)(wf + 4u * q) = u32x4{c[0], c[1], c[2], c[3]};
+    } else if constexpr (CLS == 1) {
+      or_bits(wf, r * B, c[0] | (c[1] << B) | (c[2] << (2u * B)) | (c[3] << (3u * B)), 4u * B);
+    } else if constexpr (CLS == 2) {
+      or_bits(wf, r * B, c[0] | (c[1] << B), 2u * B);
+      or_bits(wf, r * B + 2u * B, c[2] | (c[3] << B), 2u * B);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) or_bits(wf, r * B + k * B, c[k], B);
+    }
+  }
+}
+
 template <int CODEC, int FMT, int SL>
 __device__ __forceinline__ void store_pack(const Side& s, const Side& d, uint64_t i0, uint32_t nt,
                                            const uint8_t* lds, uint32_t* words, uint32_t wstride) {
@@ -1704,44 +1791,17 @@ __device__ __forceinline__ void store_pack(const Side& s, const Side& d, uint64_
         // 128-byte lines); no word image, no barrier.  Only the tile's last
         // quad may hold words past the stream, which are dropped word by word.
         const uint8_t* plane = lds + f * s.lds_stride;
-        const uint32_t quads = (nt + 3u) >> 2;
         const uint64_t start = seg_start<LY_STREAM>(d, f, i0);
         const auto rs = make_rsrc((const uint8_t*)seg_blob<LY_STREAM>(d, f) + start, d.blob_size - start);
-        const uint32_t wq = B >> 3;  // words per quad
-#pragma unroll 2
-        for (uint32_t q = threadIdx.x; q < quads; q += blockDim.x) {
-          const u32x4 v = *(const u32x4*)(plane + 16u * q);
-          const uint32_t r = 4u * q;
-          uint32_t c[4];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) c[k] = encode_fmt<CODEC, FMT>(v[k], d);
-          if (r + 4u > nt) {
-#pragma unroll
-            for (int k = 1; k < 4; ++k) c[k] = r + k < nt ? c[k] : 0u;
-          }
-          // every word starts defined: the branches below fill 1 to 4 of them
-          uint32_t w[4] = {0u, 0u, 0u, 0u};
-          if (B == 8u) {
-            w[0] = c[0] | (c[1] << 8) | (c[2] << 16) | (c[3] << 24);
-          } else if (B == 16u) {
-            w[0] = c[0] | (c[1] << 16);
-            w[1] = c[2] | (c[3] << 16);
-          } else if (B == 24u) {
-            w[0] = c[0] | (c[1] << 24);
-            w[1] = (c[1] >> 8) | (c[2] << 16);
-            w[2] = (c[2] >> 16) | (c[3] << 8);
-          } else {
-            w[0] = c[0]; w[1] = c[1]; w[2] = c[2]; w[3] = c[3];
-          }
-          const uint32_t off = 4u * wq * q;
-          if (wq * q + wq <= nw) {
-            if (B == 8u) __builtin_amdgcn_raw_buffer_store_b32(w[0], rs, off, 0, kStoreNT);
-            else if (B == 16u) __builtin_amdgcn_raw_buffer_store_b64(u32x2{w[0], w[1]}, rs, off, 0, kStoreNT);
-            else if (B == 24u) __builtin_amdgcn_raw_buffer_store_b96(u32x3{w[0], w[1], w[2]}, rs, off, 0, kStoreNT);
-            else __builtin_amdgcn_raw_buffer_store_b128(u32x4{w[0], w[1], w[2], w[3]}, rs, off, 0, kStoreNT);
-          } else {
-            for (uint32_t k = 0; k < wq && wq * q + k < nw; ++k)
-              __builtin_amdgcn_raw_buffer_store_b32(w[k], rs, off + 4u * k, 0, 0);
+        constexpr uint32_t FB = 1u + PackFmtInfo<FMT>::E + PackFmtInfo<FMT>::M;  // a fixed format's code bits
+        if constexpr (FMT != PF_RUNTIME && FB % 8u == 0u) {
+          pack_direct<FB / 8u, CODEC, FMT>(plane, nt, nw, rs, d);
+        } else {
+          switch (B) {  // block-uniform, once per field
+            case 8u: pack_direct<1, CODEC, FMT>(plane, nt, nw, rs, d); break;
+            case 16u: pack_direct<2, CODEC, FMT>(plane, nt, nw, rs, d); break;
+            case 24u: pack_direct<3, CODEC, FMT>(plane, nt, nw, rs, d); break;
+            default: pack_direct<4, CODEC, FMT>(plane, nt, nw, rs, d); break;
           }
         }
         continue;
@@ -1749,36 +1809,12 @@ __device__ __forceinline__ void store_pack(const Side& s, const Side& d, uint64_
       if (quad_plane(f)) {
         imaged = true;
         const uint8_t* plane = lds + f * s.lds_stride;
-        const uint32_t quads = (nt + 3u) >> 2;
-        for (uint32_t q = threadIdx.x; q < quads; q += blockDim.x) {
-          const u32x4 v = *(const u32x4*)(plane + 16u * q);
-          const uint32_t r = 4u * q;
-          uint32_t c[4];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) c[k] = encode_fmt<CODEC, FMT>(v[k], d);
-          if (r + 4u > nt) {  // the tile's last, partial quad: values past the tile give code 0
-#pragma unroll
-            for (int k = 1; k < 4; ++k) c[k] = r + k < nt ? c[k] : 0u;
-          }
-          if (B == 8u) {
-            wf[q] = c[0] | (c[1] << 8) | (c[2] << 16) | (c[3] << 24);
-          } else if (B == 16u) {
-            *(u32x2*)(wf + 2u * q) = u32x2{c[0] | (c[1] << 16), c[2] | (c[3] << 16)};
-          } else if (B == 32u) {
-            *(u32x4*)(wf + 4u * q) = u32x4{c[0], c[1], c[2], c[3]};
-          } else {
-            const uint32_t bit = r * B;
-            if (B < 8u) {
-              or_bits(wf, bit, c[0] | (c[1] << B) | (c[2] << (2u * B)) | (c[3] << (3u * B)), 4u * B);
-            } else if (B < 16u) {
-              or_bits(wf, bit, c[0] | (c[1] << B), 2u * B);
-              or_bits(wf, bit + 2u * B, c[2] | (c[3] << B), 2u * B);
-            } else {
-#pragma unroll
-              for (int k = 0; k < 4; ++k) or_bits(wf, bit + k * B, c[k], B);
-            }
-          }
-        }
+        // the code-width class is block-uniform: one loop per class, no
+        // width branches inside
+        if (B == 8u || B == 16u || B == 32u) pack_image<0, CODEC, FMT>(plane, nt, B, wf, d);
+        else if (B < 8u) pack_image<1, CODEC, FMT>(plane, nt, B, wf, d);
+        else if (B < 16u) pack_image<2, CODEC, FMT>(plane, nt, B, wf, d);
+        else pack_image<3, CODEC, FMT>(plane, nt, B, wf, d);
         continue;
       }
     }
