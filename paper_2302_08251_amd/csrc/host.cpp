@@ -586,7 +586,10 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     const uint64_t target = pack_direct ? 16384 : pack ? 24576
                             : line ? (D.cs == 1 && S.cs > 1 ? 32768 : 24576)  // the tile and its halo
                             : unpack ? 8192
-                            : plan.kind == PK_CONV ? 32768  // ChangeType: 32 KiB on the wider side
+                            // ChangeType: 32 KiB on the wider side; narrowing 16 KiB
+                            // (measured for f32 -> f16 / bf16 planes: 4096 values
+                            // beat 8192 by 5-8 %)
+                            : plan.kind == PK_CONV ? (S.es > D.es ? 16384 : 32768)
                             : aos2aos ? 7168
                             : merge_aos ? 16384  // one image, merged in place
                             : canonical ? 32768
