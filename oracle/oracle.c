@@ -162,7 +162,9 @@ static uint64_t ieee_widen(uint64_t bits, uint32_t Es, uint32_t Ms, uint32_t Ed,
       uint64_t frac = m & low_mask((uint32_t)p);
       return out_sign | ((uint64_t)(u + bias_d) << Md) | (frac << (Md - (uint32_t)p));
     }
-    return out_sign | (m << (Md - Ms)); /* still subnormal (Ed == Es) */
+    /* still subnormal in the target: the value m * 2^(1 - bias_s - Ms) in
+     * units of the target quantum 2^(1 - bias_d - Md) */
+    return out_sign | (m << ((uint64_t)(bias_d - bias_s) + Md - Ms));
   }
   int64_t u = (int64_t)e - bias_s;
   return out_sign | ((uint64_t)(u + bias_d) << Md) | (m << (Md - Ms));

@@ -580,3 +580,61 @@ def test_float_encode_from_f64_specials(E, M):
             quiet = (1 << (M - 1)) if M else 0
             want = inf_code | quiet | ((p >> (52 - M)) & ((1 << M) - 1))
             assert got[2 + k] == want and got[2 + len(payloads) + k] == want | sgn, (rne, hex(p))
+
+
+def decoded_reference(codes, t, E, M):
+    """Field-type bits of every finite code, from the code's exact value (Sec. 3
+    BitPackedFloatSoA: a code stands for one value, which decoding reproduces in
+    the field type).  float64 holds every value exactly (M <= 52, |exponent| well
+    inside its range); float16 / float32 conversion of a representable value is
+    exact too, which the round trip checks.  NaN and Inf codes are left out."""
+    s = (codes >> np.uint64(E + M)) & np.uint64(1)
+    e = ((codes >> np.uint64(M)) & np.uint64((1 << E) - 1)).astype(np.int64)
+    m = codes & np.uint64((1 << M) - 1)
+    bias = (1 << (E - 1)) - 1
+    finite = e != (1 << E) - 1
+    sig = np.where(e > 0, m + np.uint64(1 << M), m).astype(np.float64)
+    ex = np.where(e > 0, e - bias - M, 1 - bias - M)
+    val = np.ldexp(sig, ex) * np.where(s == 1, -1.0, 1.0)
+    val, s = val[finite], s[finite]
+    if t == "f64":
+        return finite, val.view(np.uint64)
+    narrow = val.astype(np.float16 if t == "f16" else np.float32)
+    assert np.array_equal(narrow.astype(np.float64), val)  # representable
+    if t == "f16":
+        return finite, narrow.view(np.uint16).astype(np.uint64)
+    b = narrow.view(np.uint32).astype(np.uint64)
+    assert not np.any(b & np.uint64(0xFFFF))  # a bfloat16 value
+    return finite, b >> np.uint64(16)
+
+
+def decode_formats():
+    out = []
+    for t, (Et, Mt) in (("f16", (5, 10)), ("bf16", (8, 7)), ("f64", (11, 52))):
+        for E in range(2, Et + 1):
+            for M in sorted({0, 1, 2, Mt // 2, Mt - 2, Mt - 1, Mt} - {-1}):
+                if M >= 0 and (t != "f64" or E in (2, 3, 4, 5, 8, 10, 11)):
+                    out.append((t, E, M))
+    return out
+
+
+@pytest.mark.parametrize("t,E,M", decode_formats(), ids=lambda x: str(x))
+def test_float_decode_into_f16_bf16_f64(t, E, M):
+    """Decoding into field types other than float32.  Subnormal codes whose value
+    is still subnormal in a field type with more exponent bits (E = 4, M >= 9
+    into float16) are the case that a shift by the mantissa difference alone
+    gets wrong."""
+    width = 1 + E + M
+    if width <= 16:
+        codes = np.arange(1 << width, dtype=np.uint64)
+    else:
+        rng = np.random.default_rng(width)
+        top = (1 << width) - 1
+        codes = np.concatenate([rng.integers(0, top, 1 << 15, dtype=np.uint64, endpoint=True),
+                                rng.integers(0, 1 << M, 1 << 12, dtype=np.uint64, endpoint=True),  # subnormals
+                                np.arange(0, 64, dtype=np.uint64),
+                                np.uint64(1 << (E + M)) + np.arange(0, 64, dtype=np.uint64)])
+    finite, exp = decoded_reference(codes, t, E, M)
+    got = np.array([oracle.float_decode(int(c), t, E, M) for c in codes[finite]], dtype=np.uint64)
+    bad = np.nonzero(got != exp)[0]
+    assert len(bad) == 0, (t, E, M, hex(int(codes[finite][bad[0]])), hex(int(got[bad[0]])), hex(int(exp[bad[0]])))
