@@ -380,6 +380,8 @@ llama_status make_side(const llama_view* v, Side& s, llama_scalar& user_t, llama
       break;
     case LLAMA_MAP_BITPACK_INT_SOA:
     case LLAMA_MAP_BITPACK_FLOAT_SOA:
+      if (m.kind == LLAMA_MAP_BITPACK_FLOAT_SOA && user_t != LLAMA_F32 && user_t != LLAMA_F64)
+        return fail(LLAMA_ERR_UNSUPPORTED, "the tile kernels pack f32 and f64 floats only");
       s.layout = LY_STREAM;
       s.vkind = m.kind == LLAMA_MAP_BITPACK_INT_SOA ? VK_INT : VK_FLOAT;
       s.bits = code_bits(m);
@@ -902,6 +904,16 @@ static llama_status mix_flatten(const Rec& rec, const MapDesc& m, uint64_t n, vo
   return LLAMA_OK;
 }
 
+static void set_order(const llama_view* src, const llama_view* dst, Order& o) {
+  o = Order{};
+  if (!orders_differ(src, dst)) return;
+  o.reorder = 1;
+  o.rank = dst->rank;
+  for (uint32_t d = 0; d < dst->rank; ++d) o.ext[d] = dst->extents[d];
+  o.src_col_major = src->col_major ? 1u : 0u;
+  o.dst_col_major = dst->col_major ? 1u : 0u;
+}
+
 static llama_status mix_side(const llama_view* v, MixSide& s) {
   std::memset(&s, 0, sizeof(s));
   uint32_t ng = 0, ncol = 0;
@@ -917,15 +929,91 @@ llama_status plan_mixed(const llama_view* src, const llama_view* dst, Plan& plan
   a.n = dst->n;
   a.nf = nf;
   for (uint32_t f = 0; f < nf; ++f) a.lsz[f] = (uint8_t)__builtin_ctz(scalar_size(dst->rec[f]));
-  if (orders_differ(src, dst)) {
-    a.reorder = 1;
-    a.rank = dst->rank;
-    for (uint32_t d = 0; d < dst->rank; ++d) a.ext[d] = dst->extents[d];
-    a.src_col_major = src->col_major ? 1u : 0u;
-    a.dst_col_major = dst->col_major ? 1u : 0u;
-  }
+  set_order(src, dst, a.order);
   plan.kind = PK_MIXED;
   plan.ntiles = (dst->n + kThreads - 1) / kThreads;
+  plan.grid = (uint32_t)std::min<uint64_t>(plan.ntiles, 1u << 16);
+  plan.alg_bytes = mapped_bytes(src->rec, src->map, src->n) + mapped_bytes(dst->rec, dst->map, dst->n);
+  return LLAMA_OK;
+}
+
+// ---------------------------------------------------------------- value-level copies
+
+// Float pairs a ChangeType converts (widening or narrowing in both fields),
+// or any two integer types.
+static bool conversion_ok(llama_scalar a, llama_scalar b) {
+  if (a == b) return true;
+  if (scalar_is_float(a) != scalar_is_float(b)) return false;
+  if (!scalar_is_float(a)) return true;
+  uint32_t Ea, Ma, Eb, Mb;
+  float_bits(a, Ea, Ma);
+  float_bits(b, Eb, Mb);
+  return (Eb >= Ea && Mb >= Ma) || (Eb <= Ea && Mb <= Ma);
+}
+
+// One side of a value-level copy: the kind of every leaf over the mapping
+// tree (SPLIT parts, the mapping an instrumentation forwards to), physical
+// parts flattened as for the per-leaf copy, one stream per bit-packed leaf.
+static llama_status gen_flatten(const Rec& rec, const MapDesc& m, uint64_t n, void* const* blobs, uint32_t f0,
+                                GenSide& s, uint32_t& ng, uint32_t& ncol) {
+  const uint32_t nf = (uint32_t)rec.size();
+  switch (m.kind) {
+    case LLAMA_MAP_SPLIT: {
+      const Rec r0(rec.begin(), rec.begin() + m.lanes), r1(rec.begin() + m.lanes, rec.end());
+      llama_status st = gen_flatten(r0, *m.inner, n, blobs, f0, s, ng, ncol);
+      if (st != LLAMA_OK) return st;
+      return gen_flatten(r1, *m.inner2, n, blobs + blob_count(r0, *m.inner), f0 + m.lanes, s, ng, ncol);
+    }
+    case LLAMA_MAP_FIELD_ACCESS_COUNT:
+    case LLAMA_MAP_HEATMAP:
+      return gen_flatten(rec, *m.inner, n, blobs, f0, s, ng, ncol);
+    case LLAMA_MAP_CHANGETYPE:
+      for (uint32_t j = 0; j < nf; ++j) {
+        if (!conversion_ok(rec[j], m.stored[j]))
+          return fail(LLAMA_ERR_UNSUPPORTED, "ChangeType between these leaf types is not a conversion");
+        s.kind[f0 + j] = GK_CONV;
+        s.stored_t[f0 + j] = (uint8_t)m.stored[j];
+      }
+      return mix_flatten(m.stored, *m.inner, n, blobs, f0, s.m, ng, ncol);
+    case LLAMA_MAP_BITPACK_INT_SOA:
+    case LLAMA_MAP_BITPACK_FLOAT_SOA:
+      if (ncol + nf > kMaxCols) return fail(LLAMA_ERR_UNSUPPORTED, "more than 64 storage columns in one view");
+      for (uint32_t j = 0; j < nf; ++j) {
+        const uint32_t f = f0 + j;
+        s.kind[f] = m.kind == LLAMA_MAP_BITPACK_INT_SOA ? GK_BITS_INT : GK_BITS_FLOAT;
+        s.bits[f] = (uint8_t)code_bits(m);  // at most the leaf's 64 bits
+        s.E[f] = (uint8_t)m.exp_bits;
+        s.M[f] = (uint8_t)m.man_bits;
+        s.rne[f] = (m.flags & LLAMA_FLAG_ROUND_RNE) ? 1u : 0u;
+        s.m.cidx[f] = (uint8_t)ncol;
+        s.m.col[ncol++] = (const uint8_t*)blobs[j];
+      }
+      return LLAMA_OK;
+    case LLAMA_MAP_NULL:
+      for (uint32_t j = 0; j < nf; ++j) s.kind[f0 + j] = GK_NULL;
+      return LLAMA_OK;
+    default:  // physical, Bytesplit
+      for (uint32_t j = 0; j < nf; ++j) s.kind[f0 + j] = GK_PHYS;
+      return mix_flatten(rec, m, n, blobs, f0, s.m, ng, ncol);
+  }
+}
+
+llama_status plan_generic(const llama_view* src, const llama_view* dst, Plan& plan) {
+  plan = Plan{};
+  GenArgs& a = plan.ga;
+  llama_status st;
+  uint32_t ng = 0, ncol = 0;
+  if ((st = gen_flatten(src->rec, src->map, src->n, src->blobs.data(), 0, a.src, ng, ncol)) != LLAMA_OK) return st;
+  ng = ncol = 0;
+  if ((st = gen_flatten(dst->rec, dst->map, dst->n, dst->blobs.data(), 0, a.dst, ng, ncol)) != LLAMA_OK) return st;
+  const uint32_t nf = (uint32_t)dst->rec.size();
+  a.n = dst->n;
+  a.nf = nf;
+  for (uint32_t f = 0; f < nf; ++f) a.user_t[f] = (uint8_t)dst->rec[f];
+  set_order(src, dst, a.order);
+  plan.kind = PK_GENERIC;
+  // one thread per 32 records
+  plan.ntiles = ((dst->n + 31u) / 32u + kThreads - 1) / kThreads;
   plan.grid = (uint32_t)std::min<uint64_t>(plan.ntiles, 1u << 16);
   plan.alg_bytes = mapped_bytes(src->rec, src->map, src->n) + mapped_bytes(dst->rec, dst->map, dst->n);
   return LLAMA_OK;
@@ -942,6 +1030,7 @@ llama_status launch_plan(const Plan& plan, hipStream_t st) {
     case PK_UNPACK: e = launch_unpack(plan.args, plan.unit, plan.grid, plan.lds, st); break;
     case PK_XPOSE: e = launch_xpose(plan.xa, plan.unit, plan.grid, plan.lds, st); break;
     case PK_MIXED: e = launch_mixed(plan.ma, plan.grid, st); break;
+    case PK_GENERIC: e = launch_generic(plan.ga, plan.grid, st); break;
   }
   if (e != hipSuccess) return fail(LLAMA_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
   return LLAMA_OK;
@@ -1225,6 +1314,18 @@ static void count_parts(const llama_view* v, bool store, std::vector<CopyStep>& 
 // to its inner view and counts afterwards, a NULL destination drops the
 // values, a NULL source writes zeros, a SPLIT on either side runs one copy
 // per part.
+// A pair the tile kernels or the per-leaf copy reject: the value-level copy
+// if it takes the pair, else the first planner's reason stays the error.
+static llama_status plan_generic_or_keep(const llama_view* src, const llama_view* dst, Plan& plan) {
+  const std::string why = g_error;
+  if (plan_generic(src, dst, plan) == LLAMA_OK) {
+    clear_error();
+    return LLAMA_OK;
+  }
+  g_error = why;
+  return LLAMA_ERR_UNSUPPORTED;
+}
+
 static llama_status plan_views(const llama_view* src, const llama_view* dst, const llama_launch_params* params,
                                std::vector<CopyStep>& steps) {
   if (!src || !dst) return fail(LLAMA_ERR_INVALID_ARG, "view is NULL");
@@ -1261,10 +1362,12 @@ static llama_status plan_views(const llama_view* src, const llama_view* dst, con
       }
       return LLAMA_OK;
     }
-    // any other partner: one per-leaf copy over both mapping trees, then the
-    // counters of their instrumented parts
+    // any other partner: one per-leaf copy over both mapping trees (value by
+    // value where a part is computed), then the counters of their
+    // instrumented parts
     CopyStep step;
     llama_status s = plan_mixed(src, dst, step.plan);
+    if (s == LLAMA_ERR_UNSUPPORTED) s = plan_generic_or_keep(src, dst, step.plan);
     if (s != LLAMA_OK) return s;
     steps.push_back(step);
     count_parts(src, false, steps);
@@ -1278,6 +1381,9 @@ static llama_status plan_views(const llama_view* src, const llama_view* dst, con
   else if (src->map.kind == LLAMA_MAP_NULL) s = plan_zero(dst, step.plan);  // zeros in any order
   else if (orders_differ(src, dst)) s = plan_xpose(src, dst, step.plan);
   else s = plan_copy(src, dst, params, step.plan);
+  // what the tile kernels do not move (two computed views, integer
+  // ChangeType, codes over 32 bits, ...) is copied value by value
+  if (s == LLAMA_ERR_UNSUPPORTED) s = plan_generic_or_keep(src, dst, step.plan);
   if (s != LLAMA_OK) return s;
   steps.push_back(step);
   return LLAMA_OK;

@@ -53,7 +53,7 @@ struct llama_view {
 
 namespace lm {
 
-enum PlanKind : uint32_t { PK_RAW = 0, PK_CONV = 1, PK_PACK = 2, PK_UNPACK = 3, PK_ZERO = 4, PK_XPOSE = 5, PK_MIXED = 6 };
+enum PlanKind : uint32_t { PK_RAW = 0, PK_CONV = 1, PK_PACK = 2, PK_UNPACK = 3, PK_ZERO = 4, PK_XPOSE = 5, PK_MIXED = 6, PK_GENERIC = 7 };
 
 struct Plan {
   PlanKind kind = PK_RAW;
@@ -65,6 +65,7 @@ struct Plan {
   TileArgs args{};
   XposeArgs xa{};  // PK_XPOSE
   MixArgs ma{};    // PK_MIXED
+  GenArgs ga{};    // PK_GENERIC
 };
 
 // Builds the device description of a view.  UNSUPPORTED when the tile
@@ -101,6 +102,10 @@ bool mixed_record(const Rec& r);
 // Per-leaf copy (records of mixed leaf sizes, SPLIT trees against any
 // partner, NULL parts), in either linearisation order.
 llama_status plan_mixed(const llama_view* src, const llama_view* dst, Plan& plan);
+// Value-level copy: each value loaded through the source mapping and stored
+// through the destination mapping (computed mappings on both sides, integer
+// ChangeType, bit-packed codes up to 64 bits, bit-packed f16 / bf16).
+llama_status plan_generic(const llama_view* src, const llama_view* dst, Plan& plan);
 
 // Geometry of one blob of a physical layout for Heatmap counting: records
 // come in periods of `period` bytes holding `recs` records each (AoS: one

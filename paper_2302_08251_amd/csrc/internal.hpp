@@ -172,16 +172,54 @@ struct MixSide {
   uint8_t cidx[kMaxFields];
 };
 
+// Views linearised in different orders (Sec. 2): the extents and both
+// orders, so that a destination index converts to the source's.
+struct Order {
+  uint32_t rank;
+  uint32_t reorder;               // 0: both sides use the same linear index
+  uint32_t src_col_major, dst_col_major;
+  uint64_t ext[8];
+};
+
 struct MixArgs {
   MixSide src, dst;
+  Order order;
   uint64_t n;
   uint32_t nf;
-  uint32_t rank;                  // extents, when the sides are linearised
-  uint32_t reorder;               //   in different orders (Sec. 2)
-  uint32_t src_col_major, dst_col_major;
   uint32_t pad;
-  uint64_t ext[8];
   uint8_t lsz[kMaxFields];        // log2 of each leaf's bytes
+};
+
+// A value-level copy (computed mappings on both sides, integer ChangeType,
+// bit-packed codes up to 64 bits, SPLIT trees with computed parts): every
+// value is loaded through the source mapping and stored through the
+// destination mapping.  Each leaf has its own kind, so one side may mix the
+// mapping kinds of a SPLIT tree's parts.
+enum GenKind : uint32_t {
+  GK_PHYS = 0,        // physical or Bytesplit: the leaf's bits as stored
+  GK_CONV = 1,        // ChangeType over a physical mapping of the stored record
+  GK_BITS_INT = 2,    // BitPackedIntSoA: col[cidx[f]] is leaf f's bit stream
+  GK_BITS_FLOAT = 3,  // BitPackedFloatSoA
+  GK_NULL = 4,        // loads give 0, stores are dropped
+};
+
+struct GenSide {
+  MixSide m;                      // physical groups of the tree, and the bit streams
+  uint8_t kind[kMaxFields];       // GenKind of each leaf
+  uint8_t bits[kMaxFields];       // code bits (bit-packed leaves)
+  uint8_t E[kMaxFields];          // float code exponent bits
+  uint8_t M[kMaxFields];          // float code mantissa bits
+  uint8_t rne[kMaxFields];        // float codes round to nearest even (else truncate)
+  uint8_t stored_t[kMaxFields];   // GK_CONV: stored scalar type of the leaf
+};
+
+struct GenArgs {
+  GenSide src, dst;
+  Order order;
+  uint64_t n;
+  uint32_t nf;
+  uint32_t pad;
+  uint8_t user_t[kMaxFields];    // scalar type of each leaf
 };
 
 }  // namespace lm

@@ -19,7 +19,8 @@ CFG2 = {
 }
 
 NP = {"f32": np.float32, "f64": np.float64, "i8": np.int8, "u8": np.uint8, "i16": np.int16,
-      "u16": np.uint16, "i32": np.int32, "u32": np.uint32, "i64": np.int64, "u64": np.uint64}
+      "u16": np.uint16, "i32": np.int32, "u32": np.uint32, "i64": np.int64, "u64": np.uint64,
+      "f16": np.float16, "bf16": np.uint16}
 
 
 def say(*a):

@@ -144,15 +144,25 @@ def test_copy_errors_before_gpu_work():
     assert err(lm.llama_copy, a, c) == "RECORD_MISMATCH"
     assert err(lm.llama_pack, d, a) == "UNSUPPORTED"
     assert err(lm.llama_unpack, a, d) == "UNSUPPORTED"
-    assert err(lm.llama_copy, d, e) == "UNSUPPORTED"
     assert err(lm.llama_copy_ex, a, view(F32x7, {"kind": "soa_sb"}, 100), 100) == "INVALID_ARG"
-    big = view(F32x7, {"kind": "aosoa", "lanes": 4096}, 100)
-    assert err(lm.llama_copy, a, big) == "UNSUPPORTED"
-    # leaves of several sizes copy per leaf, but a ChangeType needs one leaf type
-    het = view(["u8", "f64"], {"kind": "aos"}, 100)
-    het2 = view(["u8", "f64"], {"kind": "changetype", "stored": ["u8", "f32"], "inner": {"kind": "soa_sb"}}, 100)
-    assert err(lm.llama_copy, het, het2) == "UNSUPPORTED"
-    for v in (a, b, c, d, e, big, het, het2):
+    # every valid pair copies, within two limits: at most 8 physical parts in
+    # one SPLIT tree against a partner of another form, at most 64 storage
+    # columns (blobs, byte columns, bit streams) on one side
+
+    def tree(lo, hi):
+        if hi - lo == 1:
+            return {"kind": "aos"}
+        mid = (lo + hi) // 2
+        return {"kind": "split", "at": mid - lo, "parts": [tree(lo, mid), tree(mid, hi)]}
+
+    r16 = ["f32"] * 16
+    sp, sa = view(r16, tree(0, 16), 100), view(r16, {"kind": "aos"}, 100)
+    assert err(lm.llama_copy, sp, sa) == "UNSUPPORTED"
+    assert err(lm.llama_copy, sa, sp) == "UNSUPPORTED"
+    big = ["u8"] * 40 + ["f64"] * 4
+    g1, g2 = view(big, {"kind": "aos"}, 100), view(big, {"kind": "bytesplit", "inner": {"kind": "soa_sb"}}, 100)
+    assert err(lm.llama_copy, g1, g2) == "UNSUPPORTED"
+    for v in (a, b, c, d, e, sp, sa, g1, g2):
         lm.llama_view_destroy(v)
 
 

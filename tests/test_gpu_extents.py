@@ -83,9 +83,6 @@ def test_order_errors():
         lm.llama_copy(sv, lm.View(rec, {"kind": "aos", "col_major": True}, [6, 4], fill=0))
     assert e.value.name == "RECORD_MISMATCH"
     with pytest.raises(lm.LlamaError) as e:
-        lm.llama_copy(sv, lm.View(rec, {"kind": "bitpack_float", "exp": 8, "man": 7, "col_major": True}, [4, 6]))
-    assert e.value.name == "UNSUPPORTED"
-    with pytest.raises(lm.LlamaError) as e:
         lm.Batch([sv], [lm.View(rec, {"kind": "soa_sb", "col_major": True}, [4, 6], fill=0)])
     assert e.value.name == "UNSUPPORTED"
     # one non-unit extent: both orders coincide, the copy is linear

@@ -56,27 +56,37 @@ def test_null_source_writes_zero(n):
     assert_blobs_equal(download(dv), oracle.copy(ints, null, [], {"kind": "bitpack_int", "bits": 7}, n, fill=0xA5))
 
 
+def tree(lo, hi):
+    """A SPLIT tree with one AoS part per field in [lo, hi)."""
+    if hi - lo == 1:
+        return {"kind": "aos"}
+    mid = (lo + hi) // 2
+    return {"kind": "split", "at": mid - lo, "parts": [tree(lo, mid), tree(mid, hi)]}
+
+
 def test_null_destination_and_unsupported_pairs():
     n = 500
     planes = bits_planes(n, F32x7, seed=5)
     src_host = oracle.store_planes(F32x7, {"kind": "aos"}, planes)
     sv = gpu_view(F32x7, {"kind": "aos"}, n, src_host)
     lm.llama_copy(sv, gpu_view(F32x7, {"kind": "null"}, n))  # values dropped, nothing to write
-    # a SPLIT part the per-leaf copy cannot address (a bit-packed part against AoS)
-    packed = {"kind": "split", "at": 3, "parts": [{"kind": "aos"}, {"kind": "bitpack_float", "exp": 8, "man": 7}]}
+    # a SPLIT tree of more than 8 physical parts against a partner of another form
+    r10 = ["f32"] * 10
     with pytest.raises(lm.LlamaError) as e:
-        lm.llama_copy(sv, gpu_view(F32x7, packed, n))
+        lm.llama_copy(gpu_view(r10, {"kind": "aos"}, n, fill=0), gpu_view(r10, tree(0, 10), n))
     assert e.value.name == "UNSUPPORTED"
 
 
 def test_unsupported_split_part_launches_nothing():
-    """Part 0 (AoS -> SoA-SB) is supported, part 1 (bit-packed -> bit-packed) is not:
-    the copy is planned whole first, so the destination stays untouched."""
+    """Part 0 (AoS -> SoA-SB) is supported, part 1 (a SPLIT tree of ten parts
+    against AoS) is not: the copy is planned whole first, so the destination
+    stays untouched."""
     n = 1000
-    a = {"kind": "split", "at": 3, "parts": [{"kind": "aos"}, {"kind": "bitpack_float", "exp": 5, "man": 10}]}
-    b = {"kind": "split", "at": 3, "parts": [{"kind": "soa_sb"}, {"kind": "bitpack_float", "exp": 8, "man": 7}]}
-    sv = gpu_view(F32x7, a, n, fill=0x11)
-    dv = gpu_view(F32x7, b, n, fill=0xA5)
+    rec = ["f32"] * 12
+    a = {"kind": "split", "at": 2, "parts": [{"kind": "aos"}, tree(0, 10)]}
+    b = {"kind": "split", "at": 2, "parts": [{"kind": "soa_sb"}, {"kind": "aos"}]}
+    sv = gpu_view(rec, a, n, fill=0x11)
+    dv = gpu_view(rec, b, n, fill=0xA5)
     with pytest.raises(lm.LlamaError) as e:
         lm.llama_copy(sv, dv)
     assert e.value.name == "UNSUPPORTED"

@@ -593,10 +593,10 @@ def decoded_reference(codes, t, E, M):
     m = codes & np.uint64((1 << M) - 1)
     bias = (1 << (E - 1)) - 1
     finite = e != (1 << E) - 1
+    s, e, m = s[finite], e[finite], m[finite]
     sig = np.where(e > 0, m + np.uint64(1 << M), m).astype(np.float64)
     ex = np.where(e > 0, e - bias - M, 1 - bias - M)
     val = np.ldexp(sig, ex) * np.where(s == 1, -1.0, 1.0)
-    val, s = val[finite], s[finite]
     if t == "f64":
         return finite, val.view(np.uint64)
     narrow = val.astype(np.float16 if t == "f16" else np.float32)
