@@ -250,8 +250,16 @@ llama_status llama_view_records(const llama_view* view, uint64_t* n);
  * between the physical mappings, their Bytesplit forms and NULL, leaf by leaf;
  * padding bytes of dst are never written.  A Bytesplit side of such a record
  * may hold at most 64 bytes per record.
- * Errors: RECORD_MISMATCH (records or N differ), UNSUPPORTED (a pair the GPU
- * kernels do not cover; nothing is launched), INVALID_ARG. */
+ * Pairs the layout kernels do not move (two computed views, integer
+ * ChangeType, bit-packed codes of 33 to 64 bits, bit-packed f16 / bf16 leaves,
+ * SPLIT trees with computed parts against a partner of another form) are
+ * copied value by value: load through src's mapping, store through dst's.  A
+ * copy between two converting ChangeType views thus converts twice, and a
+ * signalling NaN comes out quiet.
+ * Errors: RECORD_MISMATCH (records or N differ), UNSUPPORTED (nothing is
+ * launched: more than 8 physical parts in one SPLIT tree against a partner of
+ * another form, or more than 64 storage columns - blobs, byte columns, bit
+ * streams - on one side), INVALID_ARG. */
 llama_status llama_copy(const llama_view* src, llama_view* dst, void* stream);
 
 /* Sec. 3 computed mappings convert values when they are stored to memory
