@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libllama_mi.so")
-SOURCES = ["host.cpp", "batch.cpp", "k_raw.hip", "k_raw4.hip", "k_conv.hip", "k_pack.hip", "k_unpack.hip", "k_batch.hip", "k_zero.hip", "k_count.hip", "k_xpose.hip", "k_mixed.hip", "k_generic.hip",
+SOURCES = ["host.cpp", "batch.cpp", "k_raw.hip", "k_raw4.hip", "k_conv.hip", "k_pack.hip", "k_unpack.hip", "k_batch.hip", "k_zero.hip", "k_count.hip", "k_xpose.hip", "k_mixed.hip", "k_generic.hip", "k_pack_planar.hip",
            "nbody.hip"]
 ARCH = os.environ.get("LLAMA_MI_ARCH", "gfx950")
 # Packed FP32 instructions are disabled for every HIP translation unit.

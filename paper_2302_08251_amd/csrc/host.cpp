@@ -456,6 +456,54 @@ static Codec codec_of(llama_scalar t) {
   }
 }
 
+// The planar path of pack: planes of 32-bit integers (SoA single- or
+// multi-blob, or AoS / AoSoA of one field) into BitPackedIntSoA streams of
+// the code widths it serves better than the tile kernels (measured on 256 Mi
+// values: B < 24 and not a multiple of 8, where the tile kernels OR codes
+// into a word image with LDS atomics).  False: the tile kernels pack.
+static bool plan_pack_planar(const llama_view* src, const llama_view* dst, Plan& plan) {
+  const MapDesc& sm = src->map;
+  const MapDesc& dm = dst->map;
+  const uint32_t F = (uint32_t)src->rec.size();
+  const llama_scalar t = src->rec[0];
+  if (dm.kind != LLAMA_MAP_BITPACK_INT_SOA || (t != LLAMA_I32 && t != LLAMA_U32) || F > kMaxCols) return false;
+  for (llama_scalar x : src->rec)
+    if (x != t) return false;
+  const uint32_t B = code_bits(dm);
+  if (B >= 24 || B % 8 == 0) return false;
+  PlanarPackArgs& a = plan.pp;
+  a = PlanarPackArgs{};
+  const uint64_t n = src->n;
+  for (uint32_t f = 0; f < F; ++f) {
+    const uint8_t* b0 = (const uint8_t*)src->blobs[0];
+    switch (sm.kind) {
+      case LLAMA_MAP_SOA_MB: a.src[f] = (const uint8_t*)src->blobs[f]; break;
+      case LLAMA_MAP_SOA_SB:
+        if (n % 4u) return false;  // planes on the 16-byte grid
+        a.src[f] = b0 + 4u * n * f;
+        break;
+      case LLAMA_MAP_AOS: case LLAMA_MAP_AOSOA:
+        if (F != 1) return false;
+        a.src[f] = b0;
+        break;
+      default: return false;
+    }
+    a.dst[f] = (uint8_t*)dst->blobs[f];
+  }
+  a.n = n;
+  a.nf = F;
+  a.bits = B;
+  plan.kind = PK_PACK_PLANAR;
+  plan.unit = 4;
+  // one wave per chunk of 2048 values, four waves per workgroup; 1024
+  // workgroups are resident at once (36 KiB of LDS each), looping over the rest
+  const uint64_t chunks = (n + 2047u) / 2048u * F;
+  plan.ntiles = chunks;
+  plan.grid = (uint32_t)std::min<uint64_t>((chunks + 3u) / 4u, 1024u);
+  plan.alg_bytes = mapped_bytes(src->rec, src->map, src->n) + mapped_bytes(dst->rec, dst->map, dst->n);
+  return true;
+}
+
 llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama_launch_params* p,
                        Plan& plan, uint32_t lds_cap, bool fill) {
   if (!src || !dst) return fail(LLAMA_ERR_INVALID_ARG, "view is NULL");
@@ -472,6 +520,8 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
   if (sstream && dstream) return fail(LLAMA_ERR_UNSUPPORTED, "copy between two bit-packed views");
   if (dstream) {
     if (S.vkind != VK_RAW) return fail(LLAMA_ERR_UNSUPPORTED, "pack needs a physical source");
+    // explicit launch parameters address the tile kernels
+    if ((!p || (p->tile_records == 0 && p->grid == 0)) && plan_pack_planar(src, dst, plan)) return LLAMA_OK;
     plan.kind = PK_PACK;
     plan.unit = 4;
     plan.args.codec = codec_of(su);
@@ -519,6 +569,11 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     if (plan.args.conv == CV_NONE)
       return fail(LLAMA_ERR_UNSUPPORTED, "the GPU path converts between the float types f64, f32, f16 and bf16 only");
   }
+  // Source loads stream past L1 with the L2 streaming hint where that was
+  // measured faster (whole copies +2.5 %, packs +10-20 %); unpacks and f64
+  // sources of a conversion keep the default policy (streaming measured
+  // 10-20 % slower there)
+  S.stream_ld = (plan.kind == PK_RAW || plan.kind == PK_PACK || (plan.kind == PK_CONV && S.es <= 4)) ? 1u : 0u;
   // Single-blob destination planes off the 128-byte line grid: line-owner
   // writes (every line written whole by one tile), with a halo of the
   // records that fill the tile's last line of each plane
@@ -583,15 +638,15 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     // tiles: about 7 KiB.
     const bool aos2aos = plan.kind == PK_RAW && mode == RM_DIRECT && S.layout == LY_AOS && D.layout == LY_AOS;
     const bool unpack = plan.kind == PK_UNPACK;
-    // direct packs: 16 KiB (measured: 4096 f32 values beat 6144 and more by
-    // 7-12 %; the LDS per workgroup then no longer limits occupancy)
-    const uint64_t target = pack_direct ? 16384 : pack ? 24576
+    // direct packs: 16 KiB, 24 KiB for 8-bit codes (measured on 256 Mi
+    // values: 4096 beat 6144 by 2-6 % at B = 16, 24, 32; 6144 beat 4096 by
+    // 20 % at B = 8).  Word-image packs: about 32 KiB with the image, see below.
+    const uint64_t target = pack_direct ? (D.bits == 8 ? 24576 : 16384) : pack ? 32768
                             : line ? (D.cs == 1 && S.cs > 1 ? 32768 : 24576)  // the tile and its halo
                             : unpack ? 8192
-                            // ChangeType: 32 KiB on the wider side; narrowing 16 KiB
-                            // (measured for f32 -> f16 / bf16 planes: 4096 values
-                            // beat 8192 by 5-8 %)
-                            : plan.kind == PK_CONV ? (S.es > D.es ? 16384 : 32768)
+                            // ChangeType: 32 KiB on the wider side; f32 -> f16 / bf16
+                            // 16 KiB (measured on planes: 4096 values beat 8192 by 5-8 %)
+                            : plan.kind == PK_CONV ? (S.es == 4 && D.es == 2 ? 16384 : 32768)
                             : aos2aos ? 7168
                             : merge_aos ? 16384  // one image, merged in place
                             : canonical ? 32768
@@ -603,6 +658,10 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     if (k < 1) k = 1;
     const uint64_t dst_cap = unpack ? 16384 : 65536;
     while (k > 1 && (gran * k > 65536 || gran * k * dst_bytes > dst_cap)) --k;
+    // a word-image pack above 32000 bytes of LDS runs one workgroup fewer per
+    // CU: three quarters of the tile then (measured at B = 31 on one plane:
+    // 3072 values 5.8 TB/s, 4096 values 5.2)
+    if (pack && !pack_direct && k > 1 && lds_total(gran * k) > 32000) k = k * 3u / 4u;
     if (line) {
       // A wave writes 63 windows of 16 bytes of one destination column per
       // step (16 / cs records each; the tile and its halo, plus one window).
@@ -1031,6 +1090,7 @@ llama_status launch_plan(const Plan& plan, hipStream_t st) {
     case PK_XPOSE: e = launch_xpose(plan.xa, plan.unit, plan.grid, plan.lds, st); break;
     case PK_MIXED: e = launch_mixed(plan.ma, plan.grid, st); break;
     case PK_GENERIC: e = launch_generic(plan.ga, plan.grid, st); break;
+    case PK_PACK_PLANAR: e = launch_pack_planar(plan.pp, plan.grid, st); break;
   }
   if (e != hipSuccess) return fail(LLAMA_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
   return LLAMA_OK;

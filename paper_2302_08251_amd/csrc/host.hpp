@@ -53,7 +53,8 @@ struct llama_view {
 
 namespace lm {
 
-enum PlanKind : uint32_t { PK_RAW = 0, PK_CONV = 1, PK_PACK = 2, PK_UNPACK = 3, PK_ZERO = 4, PK_XPOSE = 5, PK_MIXED = 6, PK_GENERIC = 7 };
+enum PlanKind : uint32_t { PK_RAW = 0, PK_CONV = 1, PK_PACK = 2, PK_UNPACK = 3, PK_ZERO = 4, PK_XPOSE = 5, PK_MIXED = 6, PK_GENERIC = 7,
+                          PK_PACK_PLANAR = 8 };
 
 struct Plan {
   PlanKind kind = PK_RAW;
@@ -66,6 +67,7 @@ struct Plan {
   XposeArgs xa{};  // PK_XPOSE
   MixArgs ma{};    // PK_MIXED
   GenArgs ga{};    // PK_GENERIC
+  PlanarPackArgs pp{};  // PK_PACK_PLANAR
 };
 
 // Builds the device description of a view.  UNSUPPORTED when the tile

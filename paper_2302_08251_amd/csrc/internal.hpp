@@ -57,6 +57,8 @@ struct Side {
   uint32_t lds_stride; // planar / stream: LDS bytes per column or field plane
   uint32_t n_mod16;    // n mod 16 (phase of single-blob planes)
   uint32_t rne;        // stream: float codes round to nearest even (else truncate)
+  uint32_t stream_ld;  // loads of this side stream past L1 with the streaming L2 hint (data read once)
+  uint32_t pad;
   uint64_t n;          // records
   uint64_t blob_size;  // bytes the mapping uses in each blob (all blobs of a side are equal)
   Div div_S;           // S
@@ -220,6 +222,16 @@ struct GenArgs {
   uint32_t nf;
   uint32_t pad;
   uint8_t user_t[kMaxFields];    // scalar type of each leaf
+};
+
+// Pack of planes of 32-bit integers into BitPackedIntSoA streams, one plane
+// and one stream per field.
+struct PlanarPackArgs {
+  const uint8_t* src[kMaxCols];  // field f's plane of n values
+  uint8_t* dst[kMaxCols];        // field f's stream of 4 * ceil(n * bits / 32) bytes
+  uint64_t n;
+  uint32_t nf;
+  uint32_t bits;                 // code bits B, 1..32: the low B bits of each value
 };
 
 }  // namespace lm

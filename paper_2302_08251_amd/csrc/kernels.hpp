@@ -252,6 +252,7 @@ hipError_t launch_zero(const TileArgs& a, uint32_t unit, uint32_t grid, hipStrea
 hipError_t launch_xpose(const XposeArgs& a, uint32_t unit, uint32_t grid, uint32_t lds, hipStream_t st);
 hipError_t launch_mixed(const MixArgs& a, uint32_t grid, hipStream_t st);
 hipError_t launch_generic(const GenArgs& a, uint32_t grid, hipStream_t st);
+hipError_t launch_pack_planar(const PlanarPackArgs& a, uint32_t grid, hipStream_t st);
 
 template <int KIND, int P0, int U>
 inline hipError_t launch_k(const TileArgs& a, uint32_t grid, uint32_t lds, hipStream_t st) {

@@ -29,6 +29,7 @@ typedef __attribute__((address_space(3))) void lds_void;
 
 constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit format, gfx9 family
 constexpr int kStoreNT = 2;             // cache policy: non-temporal (streaming) store
+constexpr int kLoadStream = 3;          // cache policy: a load of data read once (sc0 nt: no L1, streaming)
 
 __device__ __forceinline__ uint32_t wave_id() {
   return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -154,8 +155,9 @@ __device__ __forceinline__ void load_tile(const Side& s, uint64_t i0, uint32_t n
     const uint32_t chunk = grp * 64u + lane;
     if (chunk * 16u < phase + g.len) {
       if (abase + chunk * 16ull + 16ull <= s.blob_size) {
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void*)(lds + seg_lds<L>(s, seg) + grp * 1024u),
-                                                 16, chunk * 16u, 0, 0, 0);
+        lds_void* to = (lds_void*)(lds + seg_lds<L>(s, seg) + grp * 1024u);
+        if (s.stream_ld) __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, to, 16, chunk * 16u, 0, 0, kLoadStream);
+        else __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, to, 16, chunk * 16u, 0, 0, 0);
       } else {
         // The chunk crosses the end of the blob.  Buffer range checks work on
         // whole dwords, so a blob size that is not a multiple of 4 would zero
@@ -1572,10 +1574,11 @@ __device__ __forceinline__ void store_conv_planar(const Side& s, const Side& d, 
   }
 }
 
-// Narrowing on element planes (f32 -> f16 / bf16, f64 -> f32 / f16 / bf16):
-// a lane converts the 16 / ES_SRC values of one 16-byte source chunk
-// (consecutive lanes read consecutive chunks: no LDS bank conflicts) and
-// stores their 16 / ES_SRC * ES_DST bytes (8 or 4) whole.
+// Narrowing f32 -> f16 / bf16 on element planes: a lane converts the four
+// values of one 16-byte source chunk (consecutive lanes read consecutive
+// chunks: no LDS bank conflicts) and stores their 8 bytes whole.  (f64
+// sources keep store_conv_planar and 32 KiB tiles: with this form and
+// 16 KiB tiles f64 -> f32 measured 11 % slower.)
 template <int CONV>
 __device__ __forceinline__ void store_conv_planar_narrow(const Side& s, const Side& d, uint64_t i0, uint32_t nt,
                                                          const uint8_t* lds, uint32_t f) {
@@ -1620,7 +1623,7 @@ __device__ __forceinline__ void store_conv(const Side& s, const Side& d, uint64_
     constexpr uint32_t ESS = ConvInfo<CONV>::ES_SRC, ESD = ConvInfo<CONV>::ES_DST;
     if (s.cs == ESS && (s.mb || ((s.n * ESS) & 15u) == 0u) && (d.mb || ((d.n * ESD) & 15u) == 0u)) {
       for (uint32_t f = 0; f < d.ncols; ++f) {
-        if constexpr (ESS > ESD) store_conv_planar_narrow<CONV>(s, d, i0, nt, lds, f);
+        if constexpr (ESS == 4 && ESD == 2) store_conv_planar_narrow<CONV>(s, d, i0, nt, lds, f);
         else store_conv_planar<CONV>(s, d, i0, nt, lds, f);
       }
       return;

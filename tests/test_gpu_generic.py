@@ -29,7 +29,7 @@ def bpi(bits):
 def bpf(E, M, rne=False):
     d = {"kind": "bitpack_float", "exp": E, "man": M}
     if rne:
-        d["rne"] = True
+        d["round"] = "rne"
     return d
 
 
