@@ -569,11 +569,6 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     if (plan.args.conv == CV_NONE)
       return fail(LLAMA_ERR_UNSUPPORTED, "the GPU path converts between the float types f64, f32, f16 and bf16 only");
   }
-  // Source loads stream past L1 with the L2 streaming hint where that was
-  // measured faster (whole copies +2.5 %, packs +10-20 %); unpacks and f64
-  // sources of a conversion keep the default policy (streaming measured
-  // 10-20 % slower there)
-  S.stream_ld = (plan.kind == PK_RAW || plan.kind == PK_PACK || (plan.kind == PK_CONV && S.es <= 4)) ? 1u : 0u;
   // Single-blob destination planes off the 128-byte line grid: line-owner
   // writes (every line written whole by one tile), with a halo of the
   // records that fill the tile's last line of each plane

@@ -57,8 +57,6 @@ struct Side {
   uint32_t lds_stride; // planar / stream: LDS bytes per column or field plane
   uint32_t n_mod16;    // n mod 16 (phase of single-blob planes)
   uint32_t rne;        // stream: float codes round to nearest even (else truncate)
-  uint32_t stream_ld;  // loads of this side stream past L1 with the streaming L2 hint (data read once)
-  uint32_t pad;
   uint64_t n;          // records
   uint64_t blob_size;  // bytes the mapping uses in each blob (all blobs of a side are equal)
   Div div_S;           // S

@@ -230,7 +230,9 @@ __global__ __launch_bounds__(kThreads) void k_tile(const TileArgs a) {
     if constexpr (KIND == 2) {
       if (a.can_off) pack_clear_words(words, a.dst.ncols * wstride);  // 0: no word image
     }
-    if constexpr (KIND == 3) load_tile<LY_STREAM>(a.src, i0, nt, lds);
+    // streaming loads for packs and conversions from f32 or narrower (see load_tile)
+    if constexpr (KIND == 3) load_tile<LY_STREAM, 0, false>(a.src, i0, nt, lds);
+    else if constexpr (KIND == 1 && ConvInfo<P0>::ES_SRC > 4) load_tile<-1, 0, false>(a.src, i0, nt, lds);
     else load_tile(a.src, i0, nt, lds);
     wait_tile_loads();
     if constexpr (KIND == 1) phase_b_conv<P0, U>(a.src, a.dst, i0, nt, lds);
