@@ -459,8 +459,9 @@ static Codec codec_of(llama_scalar t) {
 // The planar path of pack: planes of 32-bit integers (SoA single- or
 // multi-blob, or AoS / AoSoA of one field) into BitPackedIntSoA streams of
 // the code widths it serves better than the tile kernels (measured on 256 Mi
-// values: B < 24 and not a multiple of 8, where the tile kernels OR codes
-// into a word image with LDS atomics).  False: the tile kernels pack.
+// values: B <= 27 and not a multiple of 8, 5.7-6.1 TB/s against 4.6-5.7 for
+// the tile kernels' word image with LDS atomics; from B = 28 the word image
+// is 2-4 % ahead).  False: the tile kernels pack.
 static bool plan_pack_planar(const llama_view* src, const llama_view* dst, Plan& plan) {
   const MapDesc& sm = src->map;
   const MapDesc& dm = dst->map;
@@ -470,7 +471,7 @@ static bool plan_pack_planar(const llama_view* src, const llama_view* dst, Plan&
   for (llama_scalar x : src->rec)
     if (x != t) return false;
   const uint32_t B = code_bits(dm);
-  if (B >= 24 || B % 8 == 0) return false;
+  if (B % 8 == 0 || B > 27) return false;
   PlanarPackArgs& a = plan.pp;
   a = PlanarPackArgs{};
   const uint64_t n = src->n;
@@ -495,11 +496,10 @@ static bool plan_pack_planar(const llama_view* src, const llama_view* dst, Plan&
   a.bits = B;
   plan.kind = PK_PACK_PLANAR;
   plan.unit = 4;
-  // one wave per chunk of 2048 values, four waves per workgroup; 1024
-  // workgroups are resident at once (36 KiB of LDS each), looping over the rest
+  // one wave per chunk of 2048 values, one workgroup per four chunks
   const uint64_t chunks = (n + 2047u) / 2048u * F;
   plan.ntiles = chunks;
-  plan.grid = (uint32_t)std::min<uint64_t>((chunks + 3u) / 4u, 1024u);
+  plan.grid = (uint32_t)std::min<uint64_t>((chunks + 3u) / 4u, 1u << 30);
   plan.alg_bytes = mapped_bytes(src->rec, src->map, src->n) + mapped_bytes(dst->rec, dst->map, dst->n);
   return true;
 }

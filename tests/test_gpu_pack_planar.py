@@ -1,11 +1,11 @@
 """GPU parity of the pack kernels on planes of 4-byte values (Sec. 3
 BitpackIntSoA, and BitpackFloatSoA in the fixed formats e8m7, e5m10, e8m15)
-against the oracle, whole streams bit for bit.  Integer codes of B < 24 bits
+against the oracle, whole streams bit for bit.  Integer codes of B <= 27 bits
 (not a multiple of 8) take the planar path, the rest the tile kernels;
 explicit launch parameters select the tile kernels for every width, so both
 are compared.  Sizes cover a partial last chunk of the planar path (2048
-values per chunk), one value, a chunk boundary, and waves that loop over
-several chunks and cross from one field's plane to the next."""
+values per chunk, four chunks per workgroup), one value, a chunk boundary,
+and workgroups whose four chunks span two fields' planes."""
 import numpy as np
 import pytest
 
@@ -70,9 +70,10 @@ def test_source_layouts_and_fields(n):
         check(["u32"], s, {"kind": "bitpack_int", "bits": 11}, n, planes[:1])
 
 
-def test_waves_loop_over_chunks_and_fields():
-    """4503 chunks of 2048 values over three fields against 4096 resident waves:
-    the first waves take a second chunk two planes further on."""
+def test_tiles_across_fields_and_many_chunks():
+    """1501 chunks of 2048 values per field over three fields: workgroups of
+    four chunks straddle the planes' ends (1501 is not a multiple of 4), and a
+    one-field stream of 8193 chunks ends in a partial tile."""
     n = 2048 * 1500 + 1
     rec = ["i32"] * 3
     planes = bits_planes(n, rec, seed=11)
