@@ -130,10 +130,11 @@ typedef enum llama_map_kind {
                                       with the same split point, SOA_MB or NULL
                                       a copy runs once per part; against any
                                       other partner it moves each record leaf
-                                      by leaf, provided every part is physical,
-                                      a Bytesplit of one, NULL, instrumented or
-                                      a SPLIT of such (UNSUPPORTED otherwise;
-                                      batches take no SPLIT or NULL views).   */
+                                      by leaf (value by value where a part is
+                                      computed), within 8 physical parts per
+                                      SPLIT tree and 64 storage columns per
+                                      side (UNSUPPORTED beyond; batches take no
+                                      SPLIT or NULL views).                   */
   /* Instrumentation (Sec. 4): locations, loads and stores go to `inner`;
    * every access also adds one to 64-bit counters held in extra blobs placed
    * after the inner mapping's blobs.  The caller owns those blobs and zeroes
@@ -171,10 +172,10 @@ typedef enum llama_map_kind {
                                       above 1) copy by linear index as usual; views in
                                       different orders must have the same extents
                                       (RECORD_MISMATCH otherwise), and the copy is a
-                                      record permutation that the GPU performs for
-                                      physical mappings with leaves of one size
-                                      (UNSUPPORTED for computed mappings and in
-                                      batches). */
+                                      record permutation: a tiled transpose between
+                                      physical mappings with leaves of one size, a
+                                      per-leaf or value-level copy otherwise
+                                      (UNSUPPORTED in batches). */
 #define LLAMA_FLAG_ROUND_RNE 0x2u  /* BITPACK_FLOAT: round the mantissa to nearest,
                                       ties to even (ties compare the
                                       significand's last bit: with M = 0 the
