@@ -855,6 +855,9 @@ __device__ __forceinline__ void store_split_fused16(const Side& s, const Side& d
   const uint32_t w0 = wave_id(), nw = num_waves(), lane = lane_id();
   const Div dg = make_div_dev(gpf);
   const uint32_t items = F * gpf;
+  // cache policy of the full-window stores (measured): non-temporal from
+  // multi-segment sources, plain from an AoS source
+  constexpr int kPol = SL == LY_AOS ? 0 : kStoreNT;
   for (uint32_t it = w0; it < items; it += nw) {
     const uint32_t f = fdiv(it, dg);
     const int qi = (int)((it - f * gpf) * per + lane) - (shifted ? 1 : 0);
@@ -897,7 +900,7 @@ __device__ __forceinline__ void store_split_fused16(const Side& s, const Side& d
       auto own_byte = [&](uint32_t j) { return (uint8_t)(col[k][j >> 2] >> (8u * (j & 3u))); };
       if (ph == 0u) {
         if (nrec == 16u) {
-          __builtin_amdgcn_raw_buffer_store_b128(own, rs, lo, 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b128(own, rs, lo, 0, kPol);
         } else {
           for (uint32_t j = 0; j < nrec; ++j) __builtin_amdgcn_raw_buffer_store_b8(own_byte(j), rs, lo + j, 0, 0);
         }
@@ -910,7 +913,7 @@ __device__ __forceinline__ void store_split_fused16(const Side& s, const Side& d
         const uint32_t lead = 16u - ph;       // own bytes in the window at lo - ph
         const bool has_prev = writer && q >= 1u;  // run q - 1 is in the tile (lane l - 1's)
         if (has_prev && nrec >= lead) {
-          __builtin_amdgcn_raw_buffer_store_b128(funnel16(prev, own, ph), rs, lo - ph, 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b128(funnel16(prev, own, ph), rs, lo - ph, 0, kPol);
         } else if (writer) {  // the tile's first run, or a short last run
           for (uint32_t j = 0; j < lead && j < nrec; ++j)
             __builtin_amdgcn_raw_buffer_store_b8(own_byte(j), rs, lo + j, 0, 0);
