@@ -1,5 +1,9 @@
 // Raw layout copies (no value conversion) of records with 1, 2 or 8 byte
 // leaves; 4-byte leaves are in k_raw4.hip.
+// Full-chunk stores of the raw copies: non-temporal at device scope (sc1 nt).
+// Measured: +0.6 % over the 36 layout pairs; the pack, unpack and batch
+// kernels lose with it and keep nt alone.
+#define LM_STORE_POLICY 18
 #include "kernels.hpp"
 
 namespace lm {

@@ -1,4 +1,8 @@
 // Raw layout copies of records with 4-byte leaves (f32 / i32 / u32).
+// Full-chunk stores of the raw copies: non-temporal at device scope (sc1 nt).
+// Measured: +0.6 % over the 36 layout pairs; the pack, unpack and batch
+// kernels lose with it and keep nt alone.
+#define LM_STORE_POLICY 18
 #include "kernels.hpp"
 
 namespace lm {

@@ -28,7 +28,13 @@ typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
 typedef __attribute__((address_space(3))) void lds_void;
 
 constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit format, gfx9 family
-constexpr int kStoreNT = 2;             // cache policy: non-temporal (streaming) store
+// Cache policy of full-chunk stores: non-temporal (streaming).  Device code is
+// compiled per translation unit, so a unit may define LM_STORE_POLICY before
+// including this header to choose another policy for its own kernels.
+#ifndef LM_STORE_POLICY
+#define LM_STORE_POLICY 2
+#endif
+constexpr int kStoreNT = LM_STORE_POLICY;
 constexpr int kLoadStream = 3;          // cache policy: a load of data read once (sc0 nt: no L1, streaming)
 
 __device__ __forceinline__ uint32_t wave_id() {
