@@ -318,7 +318,7 @@ llama_status autotune(llama_batch* b, uint64_t granule, uint32_t& bestT, uint32_
     double ms;
     uint32_t T, G, M;
   };
-  std::vector<Cand> cands1;  // round 1: every candidate once
+  std::vector<Cand> cands1;  // first pass: every candidate once
   for (uint32_t T : tiles) {
     if (upload(b, T) != LLAMA_OK) continue;  // e.g. a tile that does not fit in LDS
     // grids of 8, 32, 128 workgroups per CU, or one per tile (0), that one
@@ -352,7 +352,7 @@ llama_status autotune(llama_batch* b, uint64_t granule, uint32_t& bestT, uint32_
     }
   }
   if (cands1.empty()) return fail(LLAMA_ERR_UNSUPPORTED, "no tile size fits every view of the batch");
-  // Round 2: the three fastest, timed again in turn (A B C A B C ...) so that
+  // Second pass: the three fastest, timed again in turn (A B C A B C ...) so that
   // a drift of the clocks during tuning does not favour the early candidates
   std::sort(cands1.begin(), cands1.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
   const size_t nc = std::min<size_t>(3, cands1.size());

@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kThreads) void k_pack_planar(PlanarPackArgs a) {
     wave_lds_sync();
     // the chunk's 64 B words: 16 B quads, 16 B / 64 per lane rounded up; the
     // store range ends at the chunk's last word (or the stream's), so the
-    // lanes of the last round past it store nothing
+    // lanes of the last pass past it store nothing
     constexpr uint32_t kQuads = 16u * B, kPer = (kQuads + 63u) / 64u;
     const uint64_t w0 = c * 64u * B;  // the chunk's first stream word
     const uint64_t left = live ? 4u * (nw - w0) : 0u;
