@@ -688,12 +688,16 @@ llama_status plan_copy(const llama_view* src, const llama_view* dst, const llama
     }
     // Byte planes (a planar Bytesplit side) move in whole 1 KiB wave groups
     // when a tile has 1024 or 512 records.  Measured best: 1024 when both
-    // sides are byte planes, for the in-place merge into AoS and for the
-    // merge into one blob per element plane (SoA-MB: +4-6 % over 512); 512
-    // for the fused split (1024 level), the merge into AoSoA (level) and into
+    // sides are byte planes, for the in-place merge into AoS, for the merge
+    // into one blob per element plane (SoA-MB: +4-6 % over 512) and for the
+    // fused split from planar and AoSoA sources (+2.5-3.3 % timed alone; in a
+    // sequence of copies +1.5-2 % from AoSoA, level from planes); 512 for the
+    // fused split from AoS (level), the merge into AoSoA (level) and into
     // single-blob planes (1024 measured from -3 % to +4.5 %).
     if (plan.kind == PK_RAW && !lds_cap && (bs || bd) && !line) {
-      const uint64_t want = ((bs && bd) || merge_aos || (bs && D.layout == LY_PLANAR && D.mb)) ? 1024 : 512;
+      const bool split_multi = plan.args.mode == RM_SPLIT_FUSED && S.layout != LY_AOS;
+      const uint64_t want =
+          ((bs && bd) || merge_aos || (bs && D.layout == LY_PLANAR && D.mb) || split_multi) ? 1024 : 512;
       uint64_t kp = std::max<uint64_t>(1, want / gran);
       while (kp > 1 && (lds_total(gran * kp) > kMaxTileLds || (merge_aos && !in_place(gran * kp)) ||
                         gran * kp * dst_bytes > 65536))
